@@ -1,0 +1,164 @@
+/*
+ * edm.h -- C ABI of libedm, all-to-all convergent cross mapping (CCM) on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations are those of the kEDM paper (Takahashi et al., PEARC '21):
+ * Section 2.1 steps 1-4 (embedding, k-nearest-neighbour search, simplex
+ * lookup, Pearson skill), Section 3.3 Algorithms 1-2 (all-kNN table:
+ * pairwise distances, then the k smallest of each row, normalised) and
+ * Section 3.4 Algorithm 3 (batched lookup of every target through a
+ * library's table, targets grouped by their optimal embedding dimension,
+ * correlation computed without writing predictions).
+ *
+ * Conventions for every call
+ * --------------------------
+ * - Array pointers are DEVICE pointers (hipMalloc / torch CUDA tensors)
+ *   unless marked (host).  Arrays are row-major and C-contiguous in their
+ *   last dimension.  The caller owns every buffer it passes; libedm owns
+ *   only the workspace inside an edm_ctx.
+ * - Every call returns EDM_OK or a negative EDM_E_* code.  Arguments are
+ *   validated on the host before anything is enqueued, so an error return
+ *   means nothing was written.  No C++ exception crosses the ABI.
+ * - Work is enqueued asynchronously on the context's stream; outputs are
+ *   valid after edm_sync() or a synchronisation of that stream.  Exception:
+ *   edm_simplex_sweep and edm_ccm copy small host arrays to the device and
+ *   edm_ccm reads E_tgt back to the host (one stream synchronisation).
+ * - One context per stream.  Calls on one context must not overlap in time
+ *   from several host threads.
+ * - Inputs must be finite.  Kernels that read a series flag any non-finite
+ *   sample in a device status word, and edm_sync() then returns
+ *   EDM_E_NONFINITE (outputs for such series are unspecified).
+ *
+ * Notation
+ * --------
+ * A series x of length L, embedding dimension E >= 1, lag tau >= 1, horizon
+ * Tp >= 0.  Embedded point p has coordinates v_p[j] = x[p + j*tau],
+ * j = 0..E-1, and time stamp t(p) = p + (E-1)*tau; there are
+ * n = L - (E-1)*tau of them.  Query points and candidate neighbours are both
+ * p in [0, nq) with nq = n - Tp, so that a neighbour's future value exists.
+ * The neighbour ranking key is the float32 squared distance of Algorithm 1,
+ * sum over j ascending of (x[p+j*tau] - x[q+j*tau])^2 with one float32
+ * rounding after every subtraction, product and sum; ties are broken by the
+ * lower index q; q = p is excluded.  A call needs nq - 1 >= k, otherwise it
+ * returns EDM_E_SHORT.
+ */
+#ifndef EDM_H
+#define EDM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct edm_ctx edm_ctx;
+
+/* Arithmetic form of the distance stage.
+ * EDM_FORM_PLAIN : float32 VALU keys for every candidate pair.
+ * EDM_FORM_CHOSEN: reserved for the reduced-precision candidate filter with
+ *                  an exact re-rank; until it exists it behaves as PLAIN. */
+typedef enum { EDM_FORM_PLAIN = 0, EDM_FORM_CHOSEN = 1 } edm_form;
+
+enum {
+  EDM_OK = 0,
+  EDM_E_ARG = -1,       /* invalid argument (NULL pointer, E/tau/Tp/k/ld out of range) */
+  EDM_E_SHORT = -2,     /* series too short: nq - 1 < k                              */
+  EDM_E_HIP = -3,       /* a HIP runtime call or kernel failed                       */
+  EDM_E_NOMEM = -4,     /* workspace allocation failed                               */
+  EDM_E_NONFINITE = -5  /* a kernel saw a non-finite input sample (from edm_sync)    */
+};
+
+/* Largest supported embedding dimension of the fast path and for the sweep. */
+#define EDM_E_MAX 20
+/* Largest supported neighbour count k. */
+#define EDM_K_MAX 32
+/* Longest supported series (samples); a library series is staged whole in
+ * the 160 KiB local data share of one compute unit. */
+#define EDM_L_MAX 32768
+
+/* Create a context bound to an existing HIP stream (a hipStream_t passed as
+ * void*; NULL means the default stream).  The stream is borrowed, never
+ * destroyed by libedm.  The current HIP device at creation is the context's
+ * device.  Returns EDM_E_HIP when no device is usable. */
+int edm_ctx_create(edm_ctx **ctx, void *hip_stream);
+
+/* Select the arithmetic form (edm_form) for later calls. */
+int edm_ctx_set_form(edm_ctx *ctx, int form);
+
+/* Wait for the context's stream.  Returns EDM_E_HIP for an asynchronous
+ * kernel error and EDM_E_NONFINITE when a kernel flagged a non-finite input
+ * since the previous edm_sync (the flag is then cleared). */
+int edm_sync(edm_ctx *ctx);
+
+/* Text of the last error on ctx (never NULL; valid until the next call on
+ * ctx).  With ctx == NULL, the last error of edm_ctx_create on this thread. */
+const char *edm_last_error(const edm_ctx *ctx);
+
+/* Release the workspace and the context.  Synchronises its stream first. */
+void edm_ctx_destroy(edm_ctx *ctx);
+
+/* Time-delay embedding, Section 2.1 step 1.
+ * x   : float32 [L]
+ * out : float32 [n][E], n = L - (E-1)*tau, out[p][j] = x[p + j*tau]. */
+int edm_embed(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau,
+              float *out);
+
+/* All k-nearest-neighbour table of one library series, Section 2.1 step 2
+ * and Algorithms 1-2 (distances and the k smallest per row, "Normalize D_k").
+ * x    : float32 [L], L <= EDM_L_MAX
+ * E    : 1..EDM_E_MAX;  k: 1..EDM_K_MAX, 0 means E+1
+ * idx  : int32 [nq][k]  neighbour indices q, ascending by (key, q)   (required)
+ * dist : float32 [nq][k] Euclidean distances, computed in float64  (or NULL)
+ * w    : float32 [nq][k] simplex weights exp(-d_i/min d) / sum, Section 2.1
+ *        step 3; when min d = 0 the weights are 1 at zero distance and 0
+ *        elsewhere before normalising                               (or NULL)
+ * nq = L - (E-1)*tau - Tp. */
+int edm_knn(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau,
+            int32_t Tp, int32_t k, int32_t *idx, float *dist, float *w);
+
+/* Batched simplex lookup through one table, Section 2.1 step 3 and
+ * Algorithm 3, with the Pearson skill of Section 2.1 step 4 computed on the
+ * fly (Section 3.4).
+ * idx, w : the table of edm_knn, int32/float32 [nq][k]
+ * Y      : float32 [N][ldy] targets; row j must hold at least
+ *          nq + (E-1)*tau + Tp samples (ldy >= that)
+ * pred   : float32 [N][nq] predictions Yhat(p) = sum_i w_i Y[j][t(q_i)+Tp]
+ *          (or NULL)
+ * rho    : float32 [N] Pearson correlation of (Y[j][t(p)+Tp], Yhat(p)) over
+ *          p in [0, nq); NaN when either is constant               (or NULL) */
+int edm_lookup(edm_ctx *ctx, const int32_t *idx, const float *w, int64_t nq,
+               int32_t k, int32_t E, int32_t tau, int32_t Tp, const float *Y,
+               int64_t N, int64_t ldy, float *pred, float *rho);
+
+/* Simplex embedding-dimension sweep: every series predicts itself Tp steps
+ * ahead at E = 1..E_max with k = E+1 (Section 2.1: E is determined
+ * empirically; Section 3.4 uses each target's optimal E).
+ * X     : float32 [N][ldx];  L: (host) int64 [N] lengths, L[s] <= ldx
+ * rho   : float32 [N][E_max]; NaN where E is infeasible for the series
+ * E_opt : int32 [N], the smallest E attaining the largest non-NaN rho, or 0
+ *         when no E is feasible.  E_max: 1..EDM_E_MAX. */
+int edm_simplex_sweep(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N,
+                      int64_t ldx, int32_t E_max, int32_t tau, int32_t Tp,
+                      float *rho, int32_t *E_opt);
+
+/* All-to-all convergent cross mapping (Section 2.1, all pairs; Section 3.4:
+ * the library is embedded at the target's optimal E, targets are grouped by
+ * E and each library's table is built once per E and reused).
+ * X     : float32 [Nl][ldx] libraries, Lx: (host) int64 [Nl] lengths
+ * Y     : float32 [Nt][ldy] targets,   Ly: (host) int64 [Nt] lengths
+ * E_tgt : int32 [Nt] (device), 0..EDM_E_MAX; 0 marks a target without an E
+ * rho   : float32 [Nl][Nt], rho[i][j] = skill of predicting Y_j from X_i.
+ *         Pair (i, j) is defined iff E_tgt[j] >= 1, Ly[j] >= Lx[i] and the
+ *         library is long enough for k = E_tgt[j]+1; Y_j is read on the
+ *         library's time axis [0, Lx[i]).  Undefined pairs and constant
+ *         series give NaN.  Tp = 0 is the paper's cross map. */
+int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl,
+            int64_t ldx, const float *Y, const int64_t *Ly, int64_t Nt,
+            int64_t ldy, const int32_t *E_tgt, int32_t tau, int32_t Tp,
+            float *rho);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EDM_H */

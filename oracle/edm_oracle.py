@@ -56,6 +56,7 @@ __all__ = [
     "embed",
     "knn_keys",
     "knn",
+    "knn_rows",
     "weights",
     "lookup",
     "pearson",
@@ -109,47 +110,57 @@ def knn(x, E: int, tau: int, Tp: int, k: int = 0, block: int = 512):
     with the smallest (key, q), in ascending order (Algorithm 2's result).
     k = 0 means k = E + 1.  Returns (idx int32 [nq][k], key float32 [nq][k]).
     """
+    n = n_embedded(len(x), E, tau)
+    return knn_rows(x, E, tau, Tp, np.arange(max(n - Tp, 0)), k, block)
+
+
+def knn_rows(x, E: int, tau: int, Tp: int, rows, k: int = 0, block: int = 512):
+    """The rows ``rows`` of the table of ``knn`` (same definition), for
+    checking sampled query points of long series."""
     if k == 0:
         k = E + 1
     n = n_embedded(len(x), E, tau)
     m = n - Tp
     if E < 1 or tau < 1 or Tp < 0 or k < 1 or m - 1 < k:
         raise ValueError("not enough points for k neighbours")
-    idx = np.empty((m, k), dtype=np.int32)
-    key = np.empty((m, k), dtype=np.float32)
-    for p0 in range(0, m, block):
-        rows = np.arange(p0, min(m, p0 + block))
-        K = knn_keys(x, E, tau, Tp, rows)
-        for r, p in enumerate(rows):
+    rows = np.asarray(rows, dtype=np.int64)
+    idx = np.empty((rows.size, k), dtype=np.int32)
+    key = np.empty((rows.size, k), dtype=np.float32)
+    for b0 in range(0, rows.size, block):
+        blk = rows[b0:b0 + block]
+        K = knn_keys(x, E, tau, Tp, blk)
+        for r, p in enumerate(blk):
             cand = np.delete(np.arange(m), p)           # self excluded
             ck = K[r, cand]
             order = np.argsort(ck, kind="stable")[:k]   # ties keep lower q first
-            idx[p] = cand[order]
-            key[p] = ck[order]
+            idx[b0 + r] = cand[order]
+            key[b0 + r] = ck[order]
     return idx, key
 
 
-def weights(x, idx, E: int, tau: int):
+def weights(x, idx, E: int, tau: int, rows=None):
     """Simplex weights, Section 2.1 step 3, in float64.
 
     D_i = ||v_p - v_{q_i}|| from the float32 samples widened to float64,
     w_i = exp(-D_i / min_i D_i), normalised to sum to 1 ("Normalize D_k" in
-    Algorithm 2).  Returns (D [nq][k], wbar [nq][k]).
+    Algorithm 2).  Row r of ``idx`` belongs to query ``rows[r]`` (default: r).
+    Returns (D [nq][k], wbar [nq][k]).
     """
     v = embed(x, E, tau).astype(np.float64)
     idx = np.asarray(idx)
     m, k = idx.shape
+    rows = np.arange(m) if rows is None else np.asarray(rows)
     D = np.empty((m, k), dtype=np.float64)
     W = np.empty((m, k), dtype=np.float64)
-    for p in range(m):
-        diff = v[idx[p]] - v[p][None, :]
-        D[p] = np.sqrt((diff * diff).sum(axis=1))
-        dmin = D[p].min()
+    for r in range(m):
+        diff = v[idx[r]] - v[rows[r]][None, :]
+        D[r] = np.sqrt((diff * diff).sum(axis=1))
+        dmin = D[r].min()
         if dmin > 0.0:
-            w = np.exp(-D[p] / dmin)
+            w = np.exp(-D[r] / dmin)
         else:
-            w = (D[p] == 0.0).astype(np.float64)
-        W[p] = w / w.sum()
+            w = (D[r] == 0.0).astype(np.float64)
+        W[r] = w / w.sum()
     return D, W
 
 

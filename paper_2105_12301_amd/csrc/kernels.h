@@ -1,0 +1,77 @@
+// Internal interface between the host orchestration (edm_api.hip) and the
+// kernel files.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace edm {
+
+struct Mom;
+
+constexpr int kKnnThreads = 256;  // 4 waves of 64 query points per workgroup
+constexpr int kLookupThreads = 256;
+
+// Arguments of the fused embedding + distance + top-k + weights kernel.
+// One workgroup handles 256 consecutive query points of one library; the
+// grid's y index is the library slot.
+struct KnnArgs {
+  const float *X;            // libraries, row `row` at X + row*ldx
+  int64_t ldx;
+  const int64_t *L_dev;      // per-row lengths (device) or nullptr -> L_uni
+  int64_t L_uni;
+  const int32_t *lib_ids;    // slot -> row of X (device) or nullptr -> row = slot
+  int32_t E, tau, Tp, k;
+  int32_t *idx;              // [slot][nq][k] or nullptr
+  float *dist;               // [slot][nq][k] or nullptr
+  float *w;                  // [slot][nq][k] or nullptr
+  int64_t tbl_stride;        // elements between consecutive slots' tables
+  Mom *mom;                  // sweep: per-block co-moments of the self-prediction, or nullptr
+  int32_t mom_blocks;        // blocks per (row, E) in mom
+  int32_t E_max;             // sweep: number of E slots per row in mom
+  int *status;               // device status word (bit 0: non-finite input)
+};
+
+// Launch the kNN kernel for `nslots` libraries whose longest series has
+// `L_max` samples.  Returns a hipError_t.
+hipError_t launch_knn(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t st);
+
+// Arguments of the batched lookup + on-the-fly Pearson kernel.  One
+// workgroup handles one library table and a tile of targets.
+struct LookupArgs {
+  const int32_t *idx;        // [slot][nq][k]
+  const float *w;            // [slot][nq][k]
+  int64_t tbl_stride;
+  const int32_t *lib_ids;    // slot -> library id (rho row, Lx index); nullptr -> slot
+  const int64_t *Lx_dev;     // library lengths (device) or nullptr -> Lx_uni
+  int64_t Lx_uni;
+  int32_t E, tau, Tp, k;
+  const float *Y;            // targets, row j at Y + j*ldy
+  int64_t ldy;
+  const int64_t *Ly_dev;     // target lengths (device) or nullptr -> every target long enough
+  const int32_t *tgt_ids;    // bucket position -> target id (device) or nullptr -> identity
+  int32_t ntgt;
+  float *rho;                // rho[lib*ldrho + tgt] or nullptr
+  int64_t ldrho;
+  float *pred;               // pred[tgt*ldpred + p] (single table only) or nullptr
+  int64_t ldpred;
+  int *status;
+};
+
+hipError_t launch_lookup(const LookupArgs &a, int nslots, int64_t m_max, hipStream_t st);
+
+// Sweep epilogue: merge the per-block moments into rho[N][E_max] and pick
+// E_opt (smallest E with the largest non-NaN rho).
+hipError_t launch_sweep_finalize(const Mom *mom, int32_t mom_blocks, const int64_t *L_dev,
+                                 int64_t N, int32_t E_max, int32_t tau, int32_t Tp, float *rho,
+                                 int32_t *E_opt, hipStream_t st);
+
+hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
+hipError_t launch_embed(const float *x, int64_t L, int32_t E, int32_t tau, float *out,
+                        int *status, hipStream_t st);
+
+// Size in bytes of one Mom record (for workspace sizing on the host).
+constexpr size_t kMomBytes = 6 * sizeof(double);
+
+}  // namespace edm

@@ -1,0 +1,94 @@
+// Small kernels: E-sweep epilogue, fill, and the stand-alone embedding.
+#include "../../include/edm.h"
+#include "device_common.h"
+#include "kernels.h"
+
+namespace edm {
+namespace {
+
+// One thread per series: merge the per-block co-moments of each E, write
+// rho (NaN where E is infeasible or a side is constant) and pick the smallest
+// E with the largest non-NaN rho (0 if none).  The selection is made on the
+// float64 correlation before it is rounded for output.
+__global__ void k_sweep_finalize(const Mom *__restrict__ mom, int32_t mom_blocks,
+                                 const int64_t *__restrict__ L, int64_t N, int32_t E_max,
+                                 int32_t tau, int32_t Tp, float *__restrict__ rho,
+                                 int32_t *__restrict__ E_opt) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  double best = -__builtin_inf();
+  int best_e = 0;
+  for (int E = 1; E <= E_max; ++E) {
+    const int64_t m = L[s] - static_cast<int64_t>(E - 1) * tau - Tp;
+    double r = __builtin_nan("");
+    if (m - 1 >= E + 1) {
+      const int nb = static_cast<int>((m + kKnnThreads - 1) / kKnnThreads);
+      const Mom *base = mom + (s * E_max + (E - 1)) * static_cast<int64_t>(mom_blocks);
+      Mom t = base[0];
+      for (int b = 1; b < nb; ++b) t = mom_merge(t, base[b]);
+      r = mom_rho(t);
+    }
+    rho[s * E_max + (E - 1)] = static_cast<float>(r);
+    if (r == r && r > best) {
+      best = r;
+      best_e = E;
+    }
+  }
+  E_opt[s] = best_e;
+}
+
+__global__ void k_fill(float *__restrict__ p, int64_t n, float v) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+// out[p][j] = x[p + j*tau]; consecutive threads write consecutive elements.
+__global__ void k_embed(const float *__restrict__ x, int64_t n, int32_t E, int32_t tau,
+                        float *__restrict__ out, int *status) {
+  const int64_t total = n * E;
+  bool bad = false;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t p = e / E;
+    const int j = static_cast<int>(e - p * E);
+    const float v = x[p + static_cast<int64_t>(j) * tau];
+    bad |= !isfinite(v);
+    out[e] = v;
+  }
+  if (bad) atomicOr(status, 1);
+}
+
+unsigned grid_for(int64_t n, int threads) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > 65536) b = 65536;
+  return static_cast<unsigned>(b);
+}
+
+}  // namespace
+
+hipError_t launch_sweep_finalize(const Mom *mom, int32_t mom_blocks, const int64_t *L_dev,
+                                 int64_t N, int32_t E_max, int32_t tau, int32_t Tp, float *rho,
+                                 int32_t *E_opt, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sweep_finalize, dim3(grid_for(N, 64)), dim3(64), 0, st, mom, mom_blocks,
+                     L_dev, N, E_max, tau, Tp, rho, E_opt);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_embed(const float *x, int64_t L, int32_t E, int32_t tau, float *out,
+                        int *status, hipStream_t st) {
+  const int64_t n = L - static_cast<int64_t>(E - 1) * tau;
+  hipLaunchKernelGGL(k_embed, dim3(grid_for(n * E, 256)), dim3(256), 0, st, x, n, E, tau, out,
+                     status);
+  return hipGetLastError();
+}
+
+}  // namespace edm

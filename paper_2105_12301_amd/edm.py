@@ -1,0 +1,253 @@
+"""Thin Python binding of libedm (include/edm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libedm.so``.  Tensors must be CUDA (HIP) tensors of the stated dtype and
+C-contiguous; work is enqueued on torch's current stream of the tensor's
+device.  There is no fallback: if ``libedm.so`` is missing or fails to load,
+every call raises.
+
+Functions mirror the C ABI names: ``edm_embed``, ``edm_knn``, ``edm_lookup``,
+``edm_simplex_sweep``, ``edm_ccm`` (plus ``Context`` for the edm_ctx calls).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libedm.so")
+
+EDM_OK = 0
+EDM_E_ARG = -1
+EDM_E_SHORT = -2
+EDM_E_HIP = -3
+EDM_E_NOMEM = -4
+EDM_E_NONFINITE = -5
+EDM_FORM_PLAIN = 0
+EDM_FORM_CHOSEN = 1
+E_MAX = 20
+K_MAX = 32
+L_MAX = 32768
+
+EXPORTS = (
+    "edm_ctx_create", "edm_ctx_set_form", "edm_sync", "edm_last_error",
+    "edm_ctx_destroy", "edm_embed", "edm_knn", "edm_lookup",
+    "edm_simplex_sweep", "edm_ccm",
+)
+
+
+class EdmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libedm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+_p = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libedm.so and declare its signatures (no GPU needed to load)."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_2105_12301_amd.build`")
+        lib = ctypes.CDLL(path)
+        lib.edm_ctx_create.argtypes = [ctypes.POINTER(_p), _p]
+        lib.edm_ctx_set_form.argtypes = [_p, ctypes.c_int]
+        lib.edm_sync.argtypes = [_p]
+        lib.edm_last_error.argtypes = [_p]
+        lib.edm_last_error.restype = ctypes.c_char_p
+        lib.edm_ctx_destroy.argtypes = [_p]
+        lib.edm_ctx_destroy.restype = None
+        lib.edm_embed.argtypes = [_p, _p, _i64, _i32, _i32, _p]
+        lib.edm_knn.argtypes = [_p, _p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p]
+        lib.edm_lookup.argtypes = [_p, _p, _p, _i64, _i32, _i32, _i32, _i32, _p, _i64, _i64, _p, _p]
+        lib.edm_simplex_sweep.argtypes = [_p, _p, _p, _i64, _i64, _i32, _i32, _i32, _p, _p]
+        lib.edm_ccm.argtypes = [_p, _p, _p, _i64, _i64, _p, _p, _i64, _i64, _p, _i32, _i32, _p]
+        for name in EXPORTS:
+            if name not in ("edm_last_error", "edm_ctx_destroy"):
+                getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+def _check(rc: int, ctx_handle=None):
+    if rc != EDM_OK:
+        lib = load_library()
+        msg = lib.edm_last_error(ctx_handle).decode(errors="replace")
+        raise EdmError(rc, msg)
+
+
+def _dev_ptr(t, dtype, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host_i64(a, n, name):
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.int64))
+    if arr.shape != (n,):
+        raise ValueError(f"{name} must have shape ({n},)")
+    return arr
+
+
+class Context:
+    """An edm_ctx bound to a torch stream (default: the current stream)."""
+
+    def __init__(self, device=None, stream=None, form: int = EDM_FORM_PLAIN):
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libedm needs a HIP GPU; none is visible")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            _check(lib.edm_ctx_create(ctypes.byref(h), ctypes.c_void_p(self.stream.cuda_stream)))
+        self._h = h
+        self.set_form(form)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_form(self, form: int):
+        _check(load_library().edm_ctx_set_form(self._h, int(form)), self._h)
+        self.form = int(form)
+
+    def sync(self):
+        _check(load_library().edm_sync(self._h), self._h)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().edm_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+_default = {}
+
+
+def default_context(device=None) -> Context:
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+    stream = torch.cuda.current_stream(dev)
+    key = (dev, stream.cuda_stream)
+    ctx = _default.get(key)
+    if ctx is None:
+        ctx = Context(device=dev, stream=stream)
+        _default[key] = ctx
+    return ctx
+
+
+def n_query(L: int, E: int, tau: int, Tp: int) -> int:
+    return int(L) - (int(E) - 1) * int(tau) - int(Tp)
+
+
+def edm_embed(x, E: int, tau: int = 1, out=None, ctx: Context | None = None):
+    ctx = ctx or default_context(x.device)
+    L = x.shape[0]
+    n = L - (E - 1) * tau
+    if out is None:
+        out = torch.empty((max(n, 0), E), dtype=torch.float32, device=x.device)
+    _check(load_library().edm_embed(ctx.handle, _dev_ptr(x, torch.float32, "x"), L, E, tau,
+                                    _dev_ptr(out, torch.float32, "out")), ctx.handle)
+    return out
+
+
+def edm_knn(x, E: int, tau: int = 1, Tp: int = 0, k: int = 0, want_dist=True, want_w=True,
+            ctx: Context | None = None):
+    """Returns (idx int32 [nq][k], dist float32 or None, w float32 or None)."""
+    ctx = ctx or default_context(x.device)
+    L = x.shape[0]
+    kk = k if k else E + 1
+    nq = max(n_query(L, E, tau, Tp), 0)
+    idx = torch.empty((nq, kk), dtype=torch.int32, device=x.device)
+    dist = torch.empty((nq, kk), dtype=torch.float32, device=x.device) if want_dist else None
+    w = torch.empty((nq, kk), dtype=torch.float32, device=x.device) if want_w else None
+    _check(load_library().edm_knn(ctx.handle, _dev_ptr(x, torch.float32, "x"), L, E, tau, Tp, k,
+                                  _dev_ptr(idx, torch.int32, "idx"),
+                                  _dev_ptr(dist, torch.float32, "dist"),
+                                  _dev_ptr(w, torch.float32, "w")), ctx.handle)
+    return idx, dist, w
+
+
+def edm_lookup(idx, w, Y, E: int, tau: int = 1, Tp: int = 0, want_pred=False, want_rho=True,
+               ctx: Context | None = None):
+    """Returns (pred float32 [N][nq] or None, rho float32 [N] or None)."""
+    ctx = ctx or default_context(Y.device)
+    nq, k = idx.shape
+    if Y.dim() == 1:
+        Y = Y.unsqueeze(0)
+    N, ldy = Y.shape
+    pred = torch.empty((N, nq), dtype=torch.float32, device=Y.device) if want_pred else None
+    rho = torch.empty((N,), dtype=torch.float32, device=Y.device) if want_rho else None
+    _check(load_library().edm_lookup(ctx.handle, _dev_ptr(idx, torch.int32, "idx"),
+                                     _dev_ptr(w, torch.float32, "w"), nq, k, E, tau, Tp,
+                                     _dev_ptr(Y, torch.float32, "Y"), N, ldy,
+                                     _dev_ptr(pred, torch.float32, "pred"),
+                                     _dev_ptr(rho, torch.float32, "rho")), ctx.handle)
+    return pred, rho
+
+
+def edm_simplex_sweep(X, lengths=None, E_max: int = E_MAX, tau: int = 1, Tp: int = 1,
+                      ctx: Context | None = None):
+    """Returns (rho float32 [N][E_max], E_opt int32 [N])."""
+    ctx = ctx or default_context(X.device)
+    N, ldx = X.shape
+    L = _host_i64(np.full(N, ldx) if lengths is None else lengths, N, "lengths")
+    rho = torch.empty((N, E_max), dtype=torch.float32, device=X.device)
+    E_opt = torch.empty((N,), dtype=torch.int32, device=X.device)
+    _check(load_library().edm_simplex_sweep(
+        ctx.handle, _dev_ptr(X, torch.float32, "X"), L.ctypes.data_as(_p), N, ldx, E_max, tau, Tp,
+        _dev_ptr(rho, torch.float32, "rho"), _dev_ptr(E_opt, torch.int32, "E_opt")), ctx.handle)
+    return rho, E_opt
+
+
+def edm_ccm(X, E_tgt, Y=None, Lx=None, Ly=None, tau: int = 1, Tp: int = 0, rho=None,
+            ctx: Context | None = None):
+    """All-to-all CCM; returns rho float32 [Nl][Nt] (rho[i][j]: library i, target j)."""
+    ctx = ctx or default_context(X.device)
+    if Y is None:
+        Y = X
+        if Ly is None:
+            Ly = Lx
+    Nl, ldx = X.shape
+    Nt, ldy = Y.shape
+    Lx = _host_i64(np.full(Nl, ldx) if Lx is None else Lx, Nl, "Lx")
+    Ly = _host_i64(np.full(Nt, ldy) if Ly is None else Ly, Nt, "Ly")
+    if rho is None:
+        rho = torch.empty((Nl, Nt), dtype=torch.float32, device=X.device)
+    _check(load_library().edm_ccm(
+        ctx.handle, _dev_ptr(X, torch.float32, "X"), Lx.ctypes.data_as(_p), Nl, ldx,
+        _dev_ptr(Y, torch.float32, "Y"), Ly.ctypes.data_as(_p), Nt, ldy,
+        _dev_ptr(E_tgt, torch.int32, "E_tgt"), tau, Tp, _dev_ptr(rho, torch.float32, "rho")),
+        ctx.handle)
+    return rho

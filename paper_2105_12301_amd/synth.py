@@ -8,7 +8,7 @@ result is finite.
 
 This module holds no part of the EDM method itself (no embedding, neighbour
 search, lookup or correlation): it only produces inputs.  It is the one module
-shared by the CPU oracle's tests and the GPU path's tests and benchmark.
+shared by both sides of every comparison in the tests and the benchmark.
 
 Workloads (sizes are the defaults; tests pass smaller ones):
 

@@ -1,0 +1,270 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar: neighbour index tables bit-identical; distances and weights to float32
+rounding; rho within 1e-5 absolute of the float64 oracle; E* identical except
+where the oracle's best and runner-up rho are closer than 2e-5 (a near tie
+that float32 inputs to the lookup may flip).
+"""
+import numpy as np
+import pytest
+
+from oracle import edm_oracle as O
+from paper_2105_12301_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RHO_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def edm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_12301_amd import edm as _edm
+
+    _edm.load_library()
+    return _edm
+
+
+@pytest.fixture(scope="module")
+def ctx(edm):
+    c = edm.Context(device=0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def levels(L, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.integers(0, 4, size=L) * 0.25).astype(np.float32)
+
+
+def logistic(L=1000, s=0):
+    X, _ = synth.coupled_logistic_pairs(seed=1, n_pairs=4, L=L)
+    return X[s].copy()
+
+
+KNN_CASES = [
+    # name, series, E, tau, Tp, k
+    ("logistic E1", logistic(), 1, 1, 1, 0),
+    ("logistic E2 Tp0", logistic(), 2, 1, 0, 0),
+    ("logistic E3", logistic(s=1), 3, 1, 1, 0),
+    ("logistic E5", logistic(s=3), 5, 1, 1, 0),
+    ("logistic E8 Tp0", logistic(s=5), 8, 1, 0, 0),
+    ("logistic E10", logistic(s=7), 10, 1, 1, 0),
+    ("logistic E20", logistic(600, 2), 20, 1, 1, 0),
+    ("ties E1", levels(300, 1), 1, 1, 1, 0),
+    ("ties E2", levels(300, 2), 2, 1, 0, 0),
+    ("ties E4", levels(500, 3), 4, 1, 1, 0),
+    ("ties E7", levels(257, 4), 7, 1, 1, 0),
+    ("tiled E2", synth.tiled_period(13 * 9, 13, 1), 2, 1, 1, 0),
+    ("tiled E6", synth.tiled_period(11 * 12, 11, 2), 6, 1, 0, 0),
+    ("tau2 E3", logistic(s=2), 3, 2, 1, 0),
+    ("tau3 E5 ties", levels(400, 5), 5, 3, 0, 0),
+    ("k1", logistic(s=4), 3, 1, 1, 1),
+    ("k7 E2", logistic(s=6), 2, 1, 0, 7),
+    ("k32 E4", logistic(400, 1), 4, 1, 1, 32),
+    ("min length", logistic(20, 0), 3, 1, 1, 0),       # nq = 16
+    ("nq=k+1", logistic(7, 1), 2, 1, 1, 0),            # nq = 5 = k+2 -> ok; nq-1 = 4 >= 3
+    ("nq=63", logistic(65, 1), 2, 1, 1, 0),
+    ("nq=64", logistic(66, 1), 2, 1, 1, 0),
+    ("nq=65", logistic(67, 1), 2, 1, 1, 0),
+    ("nq=256", logistic(259, 3), 3, 1, 1, 0),
+    ("nq=257", logistic(260, 3), 3, 1, 1, 0),
+    ("nq=511 E9", logistic(520, 5), 9, 1, 1, 0),
+    ("ramp E3", synth.ramp(200), 3, 1, 0, 0),
+]
+
+
+@pytest.mark.parametrize("case", KNN_CASES, ids=[c[0] for c in KNN_CASES])
+def test_knn_table_bit_exact(edm, ctx, case):
+    _, x, E, tau, Tp, k = case
+    idx, dist, w = edm.edm_knn(dev(x), E, tau, Tp, k, ctx=ctx)
+    ctx.sync()
+    oi, ok = O.knn(x, E, tau, Tp, k)
+    np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+    D, W = O.weights(x, oi, E, tau)
+    np.testing.assert_allclose(dist.cpu().numpy(), D, rtol=2e-7, atol=1e-30)
+    np.testing.assert_allclose(w.cpu().numpy(), W, rtol=0, atol=1e-6)
+
+
+def test_knn_full_length_sampled(edm, ctx):
+    # The longest supported series class (L = 20000) and the bench length
+    # (5000): sampled query rows against the oracle, which computes rows one by one.
+    for L, E, seed in ((5000, 20, 0), (20000, 3, 1)):
+        X, _, _ = synth.logistic_network(seed=seed, N=4, L=L)
+        x = X[1]
+        idx, _, w = edm.edm_knn(dev(x), E, 1, 1, ctx=ctx)
+        ctx.sync()
+        m = idx.shape[0]
+        rows = np.unique(np.r_[0, 1, 63, 64, 255, 256, m - 2, m - 1,
+                               np.random.default_rng(seed).integers(0, m, 40)])
+        oi, _ = O.knn_rows(x, E, 1, 1, rows)
+        np.testing.assert_array_equal(idx.cpu().numpy()[rows], oi)
+        _, W = O.weights(x, oi, E, 1, rows=rows)
+        np.testing.assert_allclose(w.cpu().numpy()[rows], W, rtol=0, atol=1e-6)
+
+
+def test_embed(edm, ctx):
+    x = logistic(100)
+    for E, tau in ((1, 1), (4, 2), (20, 1)):
+        out = edm.edm_embed(dev(x), E, tau, ctx=ctx)
+        ctx.sync()
+        np.testing.assert_array_equal(out.cpu().numpy(), O.embed(x, E, tau))
+
+
+@pytest.mark.parametrize("E,Tp,N", [(2, 0, 8), (3, 1, 8), (1, 0, 3), (6, 1, 17), (20, 1, 1)])
+def test_lookup_rho_and_pred(edm, ctx, E, Tp, N):
+    X, _ = synth.coupled_logistic_pairs(seed=1, n_pairs=4, L=1000)
+    Y = np.concatenate([X] * ((N + 7) // 8))[:N] + np.float32(0.0)
+    Y[N // 2:] = np.float32(1000.0) + Y[N // 2:]   # large common offset on half
+    x = X[1]
+    idx, _, w = edm.edm_knn(dev(x), E, 1, Tp, ctx=ctx)
+    pred, rho = edm.edm_lookup(idx, w, dev(Y), E, 1, Tp, want_pred=True, ctx=ctx)
+    ctx.sync()
+    oi, _ = O.knn(x, E, 1, Tp)
+    _, W = O.weights(x, oi, E, 1)
+    for j in range(N):
+        yh, ob = O.lookup(oi, W, Y[j], E, 1, Tp)
+        r = O.pearson(ob, yh)
+        assert abs(float(rho[j]) - r) <= RHO_TOL, (j, float(rho[j]), r)
+        scale = max(1.0, np.abs(Y[j]).max())
+        np.testing.assert_allclose(pred[j].cpu().numpy(), yh, rtol=0, atol=2e-6 * scale)
+
+
+def test_lookup_constant_target_is_nan(edm, ctx):
+    x = logistic(300)
+    idx, _, w = edm.edm_knn(dev(x), 2, 1, 0, ctx=ctx)
+    Y = np.stack([np.full(300, 0.7, np.float32), x])
+    _, rho = edm.edm_lookup(idx, w, dev(Y), 2, 1, 0, ctx=ctx)
+    ctx.sync()
+    assert np.isnan(float(rho[0])) and np.isfinite(float(rho[1]))
+
+
+def near_tie_ok(ro_row, e_gpu, e_orc):
+    if e_gpu == e_orc:
+        return True
+    return abs(ro_row[e_gpu - 1] - ro_row[e_orc - 1]) < 2e-5
+
+
+def test_sweep_small(edm, ctx):
+    X, _ = synth.coupled_logistic_pairs(seed=1)
+    N, L = X.shape
+    rho, Eo = edm.edm_simplex_sweep(dev(X), E_max=10, Tp=1, ctx=ctx)
+    ctx.sync()
+    ro, Eor = O.simplex_sweep(X, np.full(N, L), 10)
+    g = rho.cpu().numpy()
+    assert np.nanmax(np.abs(g - ro)) <= RHO_TOL
+    assert np.array_equal(np.isnan(g), np.isnan(ro))
+    for s in range(N):
+        assert near_tie_ok(ro[s], int(Eo[s]), int(Eor[s]))
+
+
+def test_sweep_uneven_lengths_and_infeasible_E(edm, ctx):
+    lens = np.array([12, 30, 100, 257, 600])
+    X = np.zeros((5, 600), np.float32)
+    for i, L in enumerate(lens):
+        X[i, :L] = logistic(L, i % 8)
+    rho, Eo = edm.edm_simplex_sweep(dev(X), lengths=lens, E_max=20, Tp=1, ctx=ctx)
+    ctx.sync()
+    ro, Eor = O.simplex_sweep(X, lens, 20)
+    g = rho.cpu().numpy()
+    assert np.array_equal(np.isnan(g), np.isnan(ro))
+    assert np.nanmax(np.abs(g - ro)) <= RHO_TOL
+    for s in range(5):
+        assert near_tie_ok(ro[s], int(Eo[s]), int(Eor[s]))
+
+
+@pytest.mark.parametrize("Tp", [0, 1])
+def test_ccm_small(edm, ctx, Tp):
+    X, _ = synth.coupled_logistic_pairs(seed=1)
+    N, L = X.shape
+    _, Eor = O.simplex_sweep(X, np.full(N, L), 10)
+    rho = edm.edm_ccm(dev(X), dev(Eor.astype(np.int32)), Tp=Tp, ctx=ctx)
+    ctx.sync()
+    ro = O.ccm(X, np.full(N, L), X, np.full(N, L), Eor, Tp=Tp)
+    assert np.nanmax(np.abs(rho.cpu().numpy() - ro)) <= RHO_TOL
+
+
+def test_ccm_network_subset(edm, ctx):
+    X, _, _ = synth.logistic_network(seed=2, N=40, L=700)
+    N, L = X.shape
+    Xd = dev(X)
+    _, Eg = edm.edm_simplex_sweep(Xd, E_max=20, Tp=1, ctx=ctx)
+    rho = edm.edm_ccm(Xd, Eg, ctx=ctx)
+    ctx.sync()
+    Eh = Eg.cpu().numpy()
+    rows = np.array([0, 7, 39])
+    ro = O.ccm(X, np.full(N, L), X, np.full(N, L), Eh, lib_rows=rows)
+    assert np.nanmax(np.abs(rho.cpu().numpy()[rows] - ro)) <= RHO_TOL
+
+
+def test_ccm_uneven_lengths_and_undefined_pairs(edm, ctx):
+    X, lens, E = synth.spike_trains(seed=3, N=10, L_min=150, L_max=700)
+    E = np.where(np.arange(10) == 3, 0, E).astype(np.int32)   # one target without an E
+    rho = edm.edm_ccm(dev(X), dev(E), Lx=lens, Ly=lens, ctx=ctx)
+    ctx.sync()
+    ro = O.ccm(X, lens, X, lens, E)
+    g = rho.cpu().numpy()
+    assert np.array_equal(np.isnan(g), np.isnan(ro))
+    assert np.nanmax(np.abs(g - ro)) <= RHO_TOL
+
+
+def test_ccm_distinct_library_and_target_sets(edm, ctx):
+    X, _, _ = synth.logistic_network(seed=7, N=12, L=400)
+    Xl, Yt = X[:5].copy(), X[5:].copy()
+    E = np.array([1, 2, 3, 2, 5, 1, 4], np.int32)
+    rho = edm.edm_ccm(dev(Xl), dev(E), Y=dev(Yt), ctx=ctx)
+    ctx.sync()
+    ro = O.ccm(Xl, np.full(5, 400), Yt, np.full(7, 400), E)
+    assert np.nanmax(np.abs(rho.cpu().numpy() - ro)) <= RHO_TOL
+
+
+def test_repeat_runs_bit_identical(edm, ctx):
+    X, _, _ = synth.logistic_network(seed=3, N=16, L=900)
+    Xd = dev(X)
+    r1, e1 = edm.edm_simplex_sweep(Xd, E_max=12, ctx=ctx)
+    c1 = edm.edm_ccm(Xd, e1, ctx=ctx)
+    r2, e2 = edm.edm_simplex_sweep(Xd, E_max=12, ctx=ctx)
+    c2 = edm.edm_ccm(Xd, e2, ctx=ctx)
+    ctx.sync()
+    assert torch.equal(r1.view(torch.int32), r2.view(torch.int32))
+    assert torch.equal(e1, e2)
+    assert torch.equal(c1.view(torch.int32), c2.view(torch.int32))
+
+
+def test_nonfinite_input_reported(edm, ctx):
+    x = logistic(200).copy()
+    x[50] = np.nan
+    edm.edm_knn(dev(x), 2, 1, 0, ctx=ctx)
+    with pytest.raises(edm.EdmError) as ei:
+        ctx.sync()
+    assert ei.value.code == edm.EDM_E_NONFINITE
+    ctx.sync()  # flag cleared
+
+
+@pytest.mark.slow
+def test_full_size_network_sampled(edm, ctx):
+    # The benchmark workload: 1024 logistic-network series, L = 5000, E sweep
+    # 1..20, full 1024 x 1024 CCM.  Sampled outputs are checked one by one.
+    X, _, _ = synth.logistic_network(seed=2)
+    N, L = X.shape
+    Xd = dev(X)
+    rho_s, Eg = edm.edm_simplex_sweep(Xd, E_max=20, Tp=1, ctx=ctx)
+    rho = edm.edm_ccm(Xd, Eg, ctx=ctx)
+    ctx.sync()
+    g_s, Eh, g = rho_s.cpu().numpy(), Eg.cpu().numpy(), rho.cpu().numpy()
+    assert np.all(np.isfinite(g_s)) and np.all(Eh >= 1)
+    for s, E in ((5, 1), (5, 20), (700, int(Eh[700]))):
+        r = O.simplex_rho(X[s], X[s], E, 1, 1)
+        assert abs(g_s[s, E - 1] - r) <= RHO_TOL
+    # one library row against the targets of its three most common E values
+    i = 513
+    common = np.argsort(np.bincount(Eh, minlength=21))[::-1][:3]
+    cols = np.nonzero(np.isin(Eh, common))[0][:300]
+    ro = O.ccm(X, np.full(N, L), X, np.full(N, L), Eh, lib_rows=[i], tgt_cols=cols)
+    assert np.nanmax(np.abs(g[i, cols] - ro[0])) <= RHO_TOL
