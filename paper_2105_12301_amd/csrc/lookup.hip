@@ -75,11 +75,16 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup(LookupArgs a, int T, 
 #pragma unroll
     for (int t = 0; t < kTMax; ++t) {
       if (ok[t]) {
+        // Predictions are accumulated relative to the target's first staged
+        // sample c: sum_i w_i (y_i - c) equals Yhat - c because the weights
+        // sum to one, and keeps the float32 error proportional to the
+        // target's spread rather than its level.
         const float *yt = ys + t * m;
+        const float ct = yt[0];
         float yh = 0.0f;
 #pragma unroll
-        for (int i = 0; i < K; ++i) yh = fmaf(wi[i], yt[qi[i]], yh);
-        const double o = static_cast<double>(yt[p]);
+        for (int i = 0; i < K; ++i) yh = fmaf(wi[i], yt[qi[i]] - ct, yh);
+        const double o = static_cast<double>(yt[p]) - static_cast<double>(ct);
         const double ph = static_cast<double>(yh);
         if (c == 0.0) {
           ro[t] = o;
@@ -91,7 +96,7 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup(LookupArgs a, int T, 
         soo[t] += dO * dO;
         spp[t] += dP * dP;
         sop[t] += dO * dP;
-        if (a.pred) a.pred[static_cast<int64_t>(tgt[t]) * a.ldpred + p] = yh;
+        if (a.pred) a.pred[static_cast<int64_t>(tgt[t]) * a.ldpred + p] = yh + ct;
       }
     }
     c += 1.0;
