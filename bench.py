@@ -95,11 +95,60 @@ def cpu_baseline(X, E_star, series, lib, cores, w):
 
 
 # ---------------------------------------------------------------- GPU leg --
+def batched_sweep_ops(N, L, E_max, tau, Tp, groups=((1, 8), (9, 12), (13, 15), (16, 18), (19, 20))):
+    """Algorithmic VALU ops of the batched sweep: one running key per pair and
+    group of E values costs 3 ops per lag up to the group's largest E plus one
+    compare per E of the group (pairs counted at the group's smallest E)."""
+    total = 0
+    for lo, hi in groups:
+        hi = min(hi, E_max)
+        if lo > hi:
+            break
+        m = L - (lo - 1) * tau - Tp
+        total += N * m * (m - 1) * (3 * hi + (hi - lo + 1))
+    return total
+
+
+def run_form(edm, ctx, Xd, rho, w, steps, warmup, form):
+    import torch
+
+    ctx.set_form(form)
+    stream = ctx.stream
+
+    def step():
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        rs, Es = edm.edm_simplex_sweep(Xd, E_max=w["E_max"], tau=w["tau"], Tp=w["Tp_sweep"], ctx=ctx)
+        ev[1].record(stream)
+        edm.edm_ccm(Xd, Es, tau=w["tau"], Tp=w["Tp_ccm"], rho=rho, ctx=ctx)
+        ev[2].record(stream)
+        return ev, rs, Es
+
+    for _ in range(warmup):
+        step()
+    ctx.sync()
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ev, rs, Es = step()
+        evs.append(ev)
+    ctx.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return dict(ms_per_step=wall * 1e3 / steps,
+                sweep_ms=float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
+                ccm_ms=float(np.mean([e[1].elapsed_time(e[2]) for e in evs])),
+                rs=rs.cpu().numpy(), Es=Es.cpu().numpy(), rho=rho.cpu().numpy())
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--form", choices=("plain", "chosen", "both"), default="both",
+                    help="both: time the plain form, then the chosen form; value is the chosen form's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cores", type=int, default=0, help="CPU baseline workers (0: min(16, cpus))")
     args = ap.parse_args(argv)
@@ -121,51 +170,33 @@ def main(argv=None):
     torch.cuda.set_device(dev)
     Xd = torch.from_numpy(X).to(dev)
     ctx = edm.Context(device=0)
-    stream = torch.cuda.current_stream(dev)
     rho = torch.empty((N, N), dtype=torch.float32, device=dev)
-
-    def step():
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        ev[0].record(stream)
-        rs, Es = edm.edm_simplex_sweep(Xd, E_max=w["E_max"], tau=w["tau"], Tp=w["Tp_sweep"], ctx=ctx)
-        ev[1].record(stream)
-        edm.edm_ccm(Xd, Es, tau=w["tau"], Tp=w["Tp_ccm"], rho=rho, ctx=ctx)
-        ev[2].record(stream)
-        return ev, rs, Es
-
-    for _ in range(args.warmup):
-        step()
-    ctx.sync()
-    torch.cuda.synchronize()
-    evs = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ev, rs, Es = step()
-        evs.append(ev)
-    ctx.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    sweep_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    ccm_ms = [e[1].elapsed_time(e[2]) for e in evs]
-    ms_per_step = wall * 1e3 / args.steps
     pairs = N * N
-    value = pairs / (ms_per_step / 1e3)
 
-    ops = sweep_ops(N, L, w["E_max"], w["tau"], w["Tp_sweep"])
-    sweep_s = float(np.mean(sweep_ms)) / 1e3
-    achieved = ops / sweep_s
-    E_star = Es.cpu().numpy()
-    rho_h = rho.cpu().numpy()
-    rs_h = rs.cpu().numpy()
+    forms = {"plain": [edm.EDM_FORM_PLAIN], "chosen": [edm.EDM_FORM_CHOSEN],
+             "both": [edm.EDM_FORM_PLAIN, edm.EDM_FORM_CHOSEN]}[args.form]
+    res = {}
+    for f in forms:
+        res[f] = run_form(edm, ctx, Xd, rho, w, args.steps, args.warmup, f)
+    main_form = forms[-1]
+    r = res[main_form]
+    form_name = "chosen" if main_form == edm.EDM_FORM_CHOSEN else "plain"
+    if main_form == edm.EDM_FORM_CHOSEN:
+        ops = batched_sweep_ops(N, L, w["E_max"], w["tau"], w["Tp_sweep"])
+        kernel = "k_sweep_multi (batched E sweep: fused embed+distance+top-k+weights+self-lookup), all groups of one sweep"
+    else:
+        ops = sweep_ops(N, L, w["E_max"], w["tau"], w["Tp_sweep"])
+        kernel = "k_knn (fused embed+distance+top-k+weights+self-lookup), all E of one sweep"
+    achieved = ops / (r["sweep_ms"] / 1e3)
 
     out = {
         "metric": "CCM pairs/sec at rho err <=1e-5 vs FP64 oracle; chosen vs plain form, 1 GPU",
-        "value": value,
+        "value": pairs / (r["ms_per_step"] / 1e3),
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -174,15 +205,15 @@ def main(argv=None):
         "config": {
             "workload": "logistic-network 1024 series x L=5000 float32; simplex E sweep 1..20 "
                         "(Tp=1) then full 1024x1024 CCM (Tp=0), k=E+1, self excluded",
-            "form": "plain",
+            "form": form_name,
             "global_batch": N,
             "seq_len": L,
             "parallelism": "single-gpu",
         },
-        "breakdown_ms": {"sweep": float(np.mean(sweep_ms)), "ccm": float(np.mean(ccm_ms))},
-        "E_star_hist": np.bincount(E_star, minlength=w["E_max"] + 1)[1:].tolist(),
+        "breakdown_ms": {"sweep": r["sweep_ms"], "ccm": r["ccm_ms"]},
+        "E_star_hist": np.bincount(r["Es"], minlength=w["E_max"] + 1)[1:].tolist(),
         "roofline": {
-            "kernel": "k_knn (fused embed+distance+top-k+weights+self-lookup), all E of one sweep",
+            "kernel": kernel,
             "bound": "alu",
             "achieved": achieved / 1e12,
             "peak": ALU_PEAK_OPS / 1e12,
@@ -192,24 +223,39 @@ def main(argv=None):
             "ops_per_sweep": ops,
         },
     }
+    if "plain" in [("plain" if f == edm.EDM_FORM_PLAIN else "chosen") for f in forms] and len(forms) > 1:
+        p = res[edm.EDM_FORM_PLAIN]
+        ops_p = sweep_ops(N, L, w["E_max"], w["tau"], w["Tp_sweep"])
+        out["plain"] = {
+            "value": pairs / (p["ms_per_step"] / 1e3),
+            "ms_per_step": p["ms_per_step"],
+            "breakdown_ms": {"sweep": p["sweep_ms"], "ccm": p["ccm_ms"]},
+            "roofline_frac": ops_p / (p["sweep_ms"] / 1e3) / ALU_PEAK_OPS,
+        }
+        out["speedup_vs_plain"] = p["ms_per_step"] / r["ms_per_step"]
+        same = (np.array_equal(p["rs"].view(np.int32), r["rs"].view(np.int32))
+                and np.array_equal(p["Es"], r["Es"])
+                and np.array_equal(p["rho"].view(np.int32), r["rho"].view(np.int32)))
+        out["chosen_bit_identical_to_plain"] = bool(same)
 
     if not args.no_cpu_baseline:
         cores = args.cores or min(16, os.cpu_count() or 1)
         series, lib = 0, 0
-        wall_cpu, o_sweep, o_row = cpu_baseline(X, E_star, series, lib, cores, w)
-        err_sweep = float(np.nanmax(np.abs(rs_h[series] - o_sweep)))
-        err_row = float(np.nanmax(np.abs(rho_h[lib] - o_row)))
+        wall_cpu, o_sweep, o_row = cpu_baseline(X, r["Es"], series, lib, cores, w)
+        err_sweep = float(np.nanmax(np.abs(r["rs"][series] - o_sweep)))
+        err_row = float(np.nanmax(np.abs(r["rho"][lib] - o_row)))
         out["cpu_baseline"] = {
             "value": N / wall_cpu,
             "unit": "pairs/s",
             "cores": cores,
             "kind": "oracle",
             "sample": f"series {series}: E sweep 1..20 (20 tables + self lookups) and library {lib}: "
-                      f"CCM row vs all {N} targets at their GPU-selected E* ({len(set(E_star.tolist()))} "
-                      f"tables + {N} lookups) = 1/{N} of the step; value = {N} pairs / wall "
-                      f"{wall_cpu:.1f} s",
+                      f"CCM row vs all {N} targets at their GPU-selected E* "
+                      f"({len(set(r['Es'].tolist()))} tables + {N} lookups) = 1/{N} of the step; "
+                      f"value = {N} pairs / wall {wall_cpu:.1f} s",
         }
-        out["parity"] = {"max_abs_rho_err_sweep": err_sweep, "max_abs_rho_err_ccm_row": err_row,
+        out["parity"] = {"form": form_name, "max_abs_rho_err_sweep": err_sweep,
+                         "max_abs_rho_err_ccm_row": err_row,
                          "ok": bool(err_sweep <= 1e-5 and err_row <= 1e-5)}
     print(json.dumps(out))
     ctx.close()

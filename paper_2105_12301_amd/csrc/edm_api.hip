@@ -277,6 +277,20 @@ int edm_simplex_sweep(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N,
   int64_t *L_dev = reinterpret_cast<int64_t *>(ctx->ws + off_L);
   edm::Mom *mom = reinterpret_cast<edm::Mom *>(ctx->ws + off_mom);
   EDM_RC(upload(ctx, L, sizeof(int64_t) * N, L_dev));
+  if (ctx->form == EDM_FORM_CHOSEN && tau == 1) {
+    // Batched form: one candidate scan per group of E values.
+    edm::KnnArgs a{};
+    a.X = X;
+    a.ldx = ldx;
+    a.L_dev = L_dev;
+    a.Tp = Tp;
+    a.tau = 1;
+    a.mom = mom;
+    a.mom_blocks = mom_blocks;
+    a.E_max = E_max;
+    a.status = ctx->status;
+    EDM_HIP(ctx, edm::launch_sweep_multi(a, static_cast<int>(N), L_max, ctx->stream));
+  } else {
   for (int E = 1; E <= E_max; ++E) {
     edm::KnnArgs a{};
     a.X = X;
@@ -293,6 +307,7 @@ int edm_simplex_sweep(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N,
     a.E_max = E_max;
     a.status = ctx->status;
     EDM_HIP(ctx, edm::launch_knn(a, static_cast<int>(N), L_max, ctx->stream));
+  }
   }
   EDM_HIP(ctx, edm::launch_sweep_finalize(mom, mom_blocks, L_dev, N, E_max, tau, Tp, rho, E_opt,
                                           ctx->stream));

@@ -37,6 +37,10 @@ struct KnnArgs {
 // `L_max` samples.  Returns a hipError_t.
 hipError_t launch_knn(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t st);
 
+// Batched E sweep (tau = 1): one scan per group of E values; same outputs
+// (per-block co-moments in a.mom) as one launch_knn per E in sweep mode.
+hipError_t launch_sweep_multi(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t st);
+
 // Arguments of the batched lookup + on-the-fly Pearson kernel.  One
 // workgroup handles one library table and a tile of targets.
 struct LookupArgs {

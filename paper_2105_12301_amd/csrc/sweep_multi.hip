@@ -1,0 +1,303 @@
+// Batched E sweep: one candidate scan serves a whole group of embedding
+// dimensions (kEDM paper: Section 2.1 steps 1-4 with E chosen empirically,
+// Algorithms 1-2; the batching over E is this library's own).
+//
+// The ranking key of Algorithm 1 for dimension E is the float32 sum over the
+// lags j < E in ascending order, so the key for E is exactly the key for E-1
+// plus one more rounded term.  A lane that owns query p therefore walks its
+// candidates once, extends the running sum lag by lag, and offers the partial
+// sum to the top-k list of every E in its group as it passes: the tables (and
+// so the correlations) are bit-identical to one scan per E, for
+// 3*E_hi + (E_hi - E_lo + 1) VALU ops per pair instead of sum_E (3E + 1).
+//
+// Everything else follows the per-E kernel in knn.hip: library staged in LDS,
+// one query per lane, diagonal candidate order (lane l sees q = s + l), a
+// sliding window of samples in registers, insertions under a wave-uniform
+// ballot, float64 weights of the winners, the self-prediction and its Pearson
+// co-moments reduced per block.  tau = 1 only (the sweep's lag); other lags
+// use the per-E kernel.
+#include <array>
+#include <type_traits>
+#include <utility>
+
+#include "../../include/edm.h"
+#include "device_common.h"
+#include "kernels.h"
+
+#pragma clang fp contract(off)
+
+namespace edm {
+namespace {
+
+constexpr int kUnroll = 8;
+
+template <int I0, int I1, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (I0 <= I1) {
+    f(std::integral_constant<int, I0>{});
+    static_for<I0 + 1, I1>(f);
+  }
+}
+
+// Offset of dimension E's list inside the flat register arrays of a group.
+template <int ELO>
+constexpr int list_off(int E) {
+  int o = 0;
+  for (int e = ELO; e < E; ++e) o += e + 1;
+  return o;
+}
+
+// Sorted insertion into the slice [OFF, OFF+K) of the flat lists; inserting
+// +inf leaves the slice unchanged (see knn.hip).
+template <int OFF, int K, int TOT>
+__device__ __forceinline__ void slice_insert(float (&qk)[TOT], int (&qi)[TOT], float key, int q) {
+#pragma unroll
+  for (int i = K - 1; i > 0; --i) {
+    const bool lt_prev = key < qk[OFF + i - 1];
+    const bool lt_cur = key < qk[OFF + i];
+    qi[OFF + i] = lt_prev ? qi[OFF + i - 1] : (lt_cur ? q : qi[OFF + i]);
+    qk[OFF + i] = __builtin_amdgcn_fmed3f(qk[OFF + i - 1], key, qk[OFF + i]);
+  }
+  const bool lt0 = key < qk[OFF];
+  qi[OFF] = lt0 ? q : qi[OFF];
+  qk[OFF] = lt0 ? key : qk[OFF];
+}
+
+template <int OFF, int K, int TOT>
+__device__ __forceinline__ void slice_offer(float (&qk)[TOT], int (&qi)[TOT], float key, int q,
+                                            bool valid) {
+  const bool want = valid && key < qk[OFF + K - 1];
+  if (__builtin_amdgcn_ballot_w64(want))
+    slice_insert<OFF, K, TOT>(qk, qi, want ? key : __builtin_inff(), q);
+}
+
+template <int ELO, int EHI>
+__global__ __launch_bounds__(kKnnThreads) void k_sweep_multi(KnnArgs a, int slot0) {
+  constexpr int NG = EHI - ELO + 1;
+  constexpr int TOT = list_off<ELO>(EHI + 1);
+  extern __shared__ float xs[];
+  __shared__ Mom wmom[kKnnThreads / kWave][NG];
+
+  const int row = slot0 + static_cast<int>(blockIdx.y);
+  const float *__restrict__ x = a.X + static_cast<int64_t>(row) * a.ldx;
+  const int L = static_cast<int>(a.L_dev ? a.L_dev[row] : a.L_uni);
+  const int Tp = a.Tp;
+  // m(E) = queries = candidates at dimension E (tau = 1)
+  const int m_lo = L - (ELO - 1) - Tp;
+  const int m_hi = L - (EHI - 1) - Tp;
+  if (m_lo - 1 < ELO + 1) return;  // no E of the group is feasible
+  const int blk0 = static_cast<int>(blockIdx.x) * kKnnThreads;
+  if (blk0 >= m_lo) return;
+
+  bool bad = false;
+  for (int i = threadIdx.x; i < L; i += kKnnThreads) {
+    const float v = x[i];
+    bad |= !isfinite(v);
+    xs[i] = v;
+  }
+  if (bad) atomicOr(a.status, 1);
+  __syncthreads();
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int p0 = blk0 + (threadIdx.x & ~(kWave - 1));
+  const int p = p0 + lane;
+
+  float vp[EHI];
+#pragma unroll
+  for (int j = 0; j < EHI; ++j) vp[j] = (p < m_lo && p + j < L) ? xs[p + j] : 0.0f;
+
+  float qk[TOT];
+  int qi[TOT];
+  static_for<ELO, EHI>([&](auto EC) {
+    constexpr int E = decltype(EC)::value;
+    constexpr int OFF = list_off<ELO>(E);
+    const bool act = p < L - (E - 1) - Tp;
+#pragma unroll
+    for (int i = 0; i < E + 1; ++i) {
+      qk[OFF + i] = act ? __builtin_inff() : -1.0f;
+      qi[OFF + i] = -1;
+    }
+  });
+
+  if (p0 < m_lo) {
+    // Candidates whose window may run past some E's range: per-E validity.
+    auto step_masked = [&](int s) {
+      const int q = s + lane;
+      const int qc = q < 0 ? 0 : q;
+      float acc = 0.0f;
+      static_for<0, EHI - 1>([&](auto JC) {
+        constexpr int j = decltype(JC)::value;
+        const int ix = qc + j < L ? qc + j : L - 1;
+        const float d = vp[j] - xs[ix];
+        acc = acc + d * d;
+        if constexpr (j + 1 >= ELO) {
+          constexpr int E = j + 1;
+          const bool valid = q >= 0 && q < L - (E - 1) - Tp && s != p0;
+          slice_offer<list_off<ELO>(E), E + 1, TOT>(qk, qi, acc, q, valid);
+        }
+      });
+    };
+
+    int s = -(kWave - 1);
+#pragma unroll 1
+    for (; s < 0; ++s) step_masked(s);
+    const int s_full = m_hi - (kWave - 1);  // every lane's q < m_hi: valid for all E
+    if (s + kUnroll <= s_full) {
+      float win[EHI + kUnroll - 1];
+#pragma unroll
+      for (int j = 0; j < EHI - 1; ++j) win[j] = xs[s + lane + j];
+      for (; s + kUnroll <= s_full; s += kUnroll) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) win[EHI - 1 + u] = xs[s + lane + EHI - 1 + u];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const bool notself = s + u != p0;
+          const int q = s + u + lane;
+          float acc = 0.0f;
+          float key[NG];
+          static_for<0, EHI - 1>([&](auto JC) {
+            constexpr int j = decltype(JC)::value;
+            const float d = vp[j] - win[u + j];
+            acc = acc + d * d;
+            if constexpr (j + 1 >= ELO) key[j + 1 - ELO] = acc;
+          });
+          // One wave-uniform branch for the whole group: the common step
+          // improves no list at all.
+          uint64_t any = 0;
+          static_for<ELO, EHI>([&](auto EC) {
+            constexpr int E = decltype(EC)::value;
+            any |= __builtin_amdgcn_ballot_w64(notself && key[E - ELO] < qk[list_off<ELO>(E) + E]);
+          });
+          if (any) {
+            static_for<ELO, EHI>([&](auto EC) {
+              constexpr int E = decltype(EC)::value;
+              slice_offer<list_off<ELO>(E), E + 1, TOT>(qk, qi, key[E - ELO], q, notself);
+            });
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < EHI - 1; ++j) win[j] = win[j + kUnroll];
+      }
+    }
+#pragma unroll 1
+    for (; s < m_lo; ++s) step_masked(s);
+  }
+
+  // Epilogue per E: float64 distances and weights of the winners, the
+  // self-prediction Tp ahead, and the block's co-moments.
+  const int wave = threadIdx.x / kWave;
+  static_for<ELO, EHI>([&](auto EC) {
+    constexpr int E = decltype(EC)::value;
+    constexpr int K = E + 1;
+    constexpr int OFF = list_off<ELO>(E);
+    const int mE = L - (E - 1) - Tp;
+    Mom mine = mom_zero();
+    if (p < mE && mE - 1 >= K) {
+      double D[K];
+      double dmin = __builtin_inf();
+#pragma unroll 1
+      for (int r = 0; r < K; ++r) {
+        const int q = qi[OFF] < 0 ? 0 : qi[OFF];
+        double s2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          const double d = static_cast<double>(vp[j]) - static_cast<double>(xs[q + j]);
+          s2 += d * d;
+        }
+        const double dq = sqrt(s2);
+        dmin = fmin(dmin, dq);
+#pragma unroll
+        for (int i = 0; i < K - 1; ++i) {
+          qi[OFF + i] = qi[OFF + i + 1];
+          D[i] = D[i + 1];
+        }
+        qi[OFF + K - 1] = q;
+        D[K - 1] = dq;
+      }
+      double wsum = 0.0;
+#pragma unroll 1
+      for (int r = 0; r < K; ++r) {
+        const double d = D[0];
+        const double wq = dmin > 0.0 ? exp(-d / dmin) : (d == 0.0 ? 1.0 : 0.0);
+        wsum += wq;
+#pragma unroll
+        for (int i = 0; i < K - 1; ++i) D[i] = D[i + 1];
+        D[K - 1] = wq;
+      }
+      const double inv = 1.0 / wsum;
+      const int o_off = (E - 1) + Tp;
+      double yh = 0.0;
+#pragma unroll
+      for (int i = 0; i < K; ++i) yh += (D[i] * inv) * static_cast<double>(xs[qi[OFF + i] + o_off]);
+      mine.n = 1.0;
+      mine.mo = static_cast<double>(xs[p + o_off]);
+      mine.mp = yh;
+    }
+    const Mom wv = mom_wave_reduce(mine);
+    if (lane == 0) wmom[wave][E - ELO] = wv;
+  });
+  __syncthreads();
+  if (static_cast<int>(threadIdx.x) < NG) {
+    const int E = ELO + static_cast<int>(threadIdx.x);
+    const int mE = L - (E - 1) - Tp;
+    if (mE - 1 >= E + 1 && blk0 < mE) {
+      Mom t = wmom[0][threadIdx.x];
+#pragma unroll
+      for (int w = 1; w < kKnnThreads / kWave; ++w) t = mom_merge(t, wmom[w][threadIdx.x]);
+      a.mom[(static_cast<int64_t>(row) * a.E_max + (E - 1)) * a.mom_blocks + blockIdx.x] = t;
+    }
+  }
+}
+
+// Groups of E sharing one scan: the register lists of a group hold at most
+// ~54 entries (108 VGPRs).
+constexpr int kGroups[][2] = {{1, 8}, {9, 12}, {13, 15}, {16, 18}, {19, 20}};
+
+using LaunchFn = hipError_t (*)(const KnnArgs &, dim3, size_t, int, hipStream_t);
+
+template <int ELO, int EHI>
+hipError_t launch_group(const KnnArgs &a, dim3 grid, size_t shm, int slot0, hipStream_t st) {
+  const void *fn = reinterpret_cast<const void *>(&k_sweep_multi<ELO, EHI>);
+  if (shm > 65536) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(shm));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_sweep_multi<ELO, EHI>), grid, dim3(kKnnThreads), shm, st, a, slot0);
+  return hipGetLastError();
+}
+
+// table[lo-1][hi-lo]: every (lo, hi) with lo a group start and hi inside it.
+template <int LO, size_t... I>
+constexpr std::array<LaunchFn, 8> row_for(std::index_sequence<I...>) {
+  return {{&launch_group<LO, LO + static_cast<int>(I)>...}};
+}
+
+}  // namespace
+
+hipError_t launch_sweep_multi(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t st) {
+  static const std::array<LaunchFn, 8> t1 = row_for<1>(std::make_index_sequence<8>{});
+  static const std::array<LaunchFn, 8> t9 = row_for<9>(std::make_index_sequence<4>{});
+  static const std::array<LaunchFn, 8> t13 = row_for<13>(std::make_index_sequence<3>{});
+  static const std::array<LaunchFn, 8> t16 = row_for<16>(std::make_index_sequence<3>{});
+  static const std::array<LaunchFn, 8> t19 = row_for<19>(std::make_index_sequence<2>{});
+  if (nslots <= 0) return hipSuccess;
+  const unsigned gx = static_cast<unsigned>((L_max + kKnnThreads - 1) / kKnnThreads);
+  const size_t shm = static_cast<size_t>(L_max) * sizeof(float);
+  for (const auto &g : kGroups) {
+    const int lo = g[0];
+    const int hi = g[1] < a.E_max ? g[1] : a.E_max;
+    if (lo > hi) break;
+    const std::array<LaunchFn, 8> &t = lo == 1 ? t1 : lo == 9 ? t9 : lo == 13 ? t13 : lo == 16 ? t16 : t19;
+    LaunchFn fn = t[hi - lo];
+    constexpr int kMaxY = 32768;
+    for (int s0 = 0; s0 < nslots; s0 += kMaxY) {
+      const int ny = nslots - s0 < kMaxY ? nslots - s0 : kMaxY;
+      hipError_t e = fn(a, dim3(gx, static_cast<unsigned>(ny)), shm, s0, st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+}  // namespace edm

@@ -268,3 +268,42 @@ def test_full_size_network_sampled(edm, ctx):
     cols = np.nonzero(np.isin(Eh, common))[0][:300]
     ro = O.ccm(X, np.full(N, L), X, np.full(N, L), Eh, lib_rows=[i], tgt_cols=cols)
     assert np.nanmax(np.abs(g[i, cols] - ro[0])) <= RHO_TOL
+
+
+@pytest.fixture(scope="module")
+def ctx_chosen(edm):
+    c = edm.Context(device=0, form=edm.EDM_FORM_CHOSEN)
+    yield c
+    c.close()
+
+
+def test_sweep_batched_form_bit_identical_to_plain(edm, ctx, ctx_chosen):
+    # The batched sweep extends one running key across a group of E values;
+    # the key for E is the same float32 sum, so every table and rho must match
+    # the one-scan-per-E form bit for bit (and the oracle within 1e-5).
+    X, _, _ = synth.logistic_network(seed=3, N=24, L=1200)
+    lens = np.full(24, 1200)
+    lens[[1, 5, 9, 13]] = [1100, 30, 12, 600]
+    for E_max in (20, 11, 3, 1):
+        rp, ep = edm.edm_simplex_sweep(dev(X), lengths=lens, E_max=E_max, ctx=ctx)
+        rc, ec = edm.edm_simplex_sweep(dev(X), lengths=lens, E_max=E_max, ctx=ctx_chosen)
+        ctx.sync()
+        ctx_chosen.sync()
+        assert torch.equal(rp.view(torch.int32), rc.view(torch.int32)), E_max
+        assert torch.equal(ep, ec)
+    ro, _ = O.simplex_sweep(X[[0, 5, 9, 13]], lens[[0, 5, 9, 13]], 20)
+    rc20, _ = edm.edm_simplex_sweep(dev(X), lengths=lens, E_max=20, ctx=ctx_chosen)
+    ctx_chosen.sync()
+    g = rc20.cpu().numpy()[[0, 5, 9, 13]]
+    assert np.array_equal(np.isnan(g), np.isnan(ro))
+    assert np.nanmax(np.abs(g - ro)) <= RHO_TOL
+
+
+def test_ccm_chosen_form_matches_oracle(edm, ctx_chosen):
+    X, _ = synth.coupled_logistic_pairs(seed=1)
+    N, L = X.shape
+    _, Eg = edm.edm_simplex_sweep(dev(X), E_max=10, ctx=ctx_chosen)
+    rho = edm.edm_ccm(dev(X), Eg, ctx=ctx_chosen)
+    ctx_chosen.sync()
+    ro = O.ccm(X, np.full(N, L), X, np.full(N, L), Eg.cpu().numpy())
+    assert np.nanmax(np.abs(rho.cpu().numpy() - ro)) <= RHO_TOL
