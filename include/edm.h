@@ -53,10 +53,12 @@ extern "C" {
 
 typedef struct edm_ctx edm_ctx;
 
-/* Arithmetic form of the distance stage.
- * EDM_FORM_PLAIN : float32 VALU keys for every candidate pair.
- * EDM_FORM_CHOSEN: reserved for the reduced-precision candidate filter with
- *                  an exact re-rank; until it exists it behaves as PLAIN. */
+/* Form of the computation (results are identical; only the schedule differs).
+ * EDM_FORM_PLAIN : one candidate scan per (library, E), float32 VALU keys.
+ * EDM_FORM_CHOSEN: edm_simplex_sweep with tau = 1 runs one candidate scan per
+ *                  group of E values, extending one running key (the key for
+ *                  E is the key for E-1 plus one rounded term), so tables,
+ *                  rho and E_opt are bit-identical to the plain form. */
 typedef enum { EDM_FORM_PLAIN = 0, EDM_FORM_CHOSEN = 1 } edm_form;
 
 enum {
@@ -156,6 +158,56 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl,
             int64_t ldx, const float *Y, const int64_t *Ly, int64_t Nt,
             int64_t ldy, const int32_t *E_tgt, int32_t tau, int32_t Tp,
             float *rho);
+
+/* ---------------------------------------------------------------------------
+ * Learned embedding-dimension surrogate.
+ *
+ * A small 1-D convolutional network predicts a series' optimal E from the
+ * series itself; it is trained on the E* that edm_simplex_sweep selects (the
+ * method's own E selection: Section 2.1 step 1 leaves E to be determined
+ * empirically and Section 3.4 uses each target's optimal E).  Network:
+ * conv(1->C, EDM_NET_KW) -> ReLU -> conv(C->C) -> ReLU -> conv(C->C) -> ReLU
+ * -> mean over time -> linear(C->20), zero "same" padding.  Parameters are one
+ * float32 device array of edm_net_param_count(C) values laid out as
+ * w1[C][1][KW], b1[C], w2[C][C][KW], b2[C], w3[C][C][KW], b3[C], wo[20][C],
+ * bo[20].  C: 1..64.  Series are z-scored float32 rows X[B][ldx], length L.
+ * ------------------------------------------------------------------------- */
+#define EDM_NET_KW 7
+#define EDM_NET_CLASSES 20
+#define EDM_NET_C_MAX 64
+
+/* Number of float32 parameters of the network with C channels (host only). */
+int64_t edm_net_param_count(int32_t C);
+
+/* Forward pass: logits[B][20] (float32, device); class c is E = c + 1. */
+int edm_net_forward(edm_ctx *ctx, const float *params, int32_t C, const float *X, int64_t B,
+                    int64_t L, int64_t ldx, float *logits);
+
+/* Mean softmax cross-entropy of the batch against labels[B] (int32 E in
+ * 1..20, device) and its gradient with respect to the parameters.
+ * loss: float32 scalar (device); grad: float32 [edm_net_param_count(C)]. */
+int edm_net_loss_grad(edm_ctx *ctx, const float *params, int32_t C, const float *X,
+                      const int32_t *labels, int64_t B, int64_t L, int64_t ldx, float *loss,
+                      float *grad);
+
+/* One Adam step (Kingma & Ba) in place: m, v are the moment buffers of the
+ * same length n, step >= 1 counts updates (bias correction). */
+int edm_net_adam(edm_ctx *ctx, float *params, const float *grad, float *m, float *v, int64_t n,
+                 int32_t step, float lr, float beta1, float beta2, float eps);
+
+/* E selection driven by the network: for every series s the candidate set
+ * is the m_top classes with the largest logits; if the largest softmax
+ * probability is below min_conf the candidate set is every E in 1..E_max
+ * (the plain sweep, as fallback).  The simplex skill (Tp ahead, k = E+1, the
+ * same computation as edm_simplex_sweep) is evaluated at the candidates only
+ * and E_opt[s] is the smallest E with the largest non-NaN rho among them.
+ * logits: float32 [N][20] (device); rho: float32 [N][E_max] (device), NaN
+ * where E was not evaluated or is infeasible; E_opt: int32 [N] (device);
+ * n_fallback (host, or NULL): number of series that took the full sweep.
+ * Synchronises the stream once (the candidate sets are read back). */
+int edm_select_E(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int64_t ldx,
+                 int32_t E_max, int32_t tau, int32_t Tp, const float *logits, int32_t m_top,
+                 float min_conf, float *rho, int32_t *E_opt, int64_t *n_fallback);
 
 #ifdef __cplusplus
 }

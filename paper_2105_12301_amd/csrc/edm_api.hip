@@ -16,6 +16,7 @@
 
 #include "../../include/edm.h"
 #include "kernels.h"
+#include "net_kernels.h"
 #include "validate.h"
 
 struct edm_ctx {
@@ -309,8 +310,8 @@ int edm_simplex_sweep(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N,
     EDM_HIP(ctx, edm::launch_knn(a, static_cast<int>(N), L_max, ctx->stream));
   }
   }
-  EDM_HIP(ctx, edm::launch_sweep_finalize(mom, mom_blocks, L_dev, N, E_max, tau, Tp, rho, E_opt,
-                                          ctx->stream));
+  EDM_HIP(ctx, edm::launch_sweep_finalize(mom, mom_blocks, L_dev, N, E_max, tau, Tp, nullptr, rho,
+                                          E_opt, ctx->stream));
   return EDM_OK;
 }
 
@@ -422,6 +423,131 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
       EDM_HIP(ctx, edm::launch_lookup(b, static_cast<int>(nb), m_b, ctx->stream));
     }
   }
+  return EDM_OK;
+}
+
+int64_t edm_net_param_count(int32_t C) {
+  if (C < 1 || C > EDM_NET_C_MAX) return -1;
+  return edm::net_param_count(C);
+}
+
+namespace {
+int check_net(edm_ctx *ctx, const void *params, int32_t C, const void *X, int64_t B, int64_t L,
+              int64_t ldx) {
+  if (!params || (B > 0 && !X)) return set_err(ctx, EDM_E_ARG, "NULL pointer");
+  if (C < 1 || C > EDM_NET_C_MAX) return set_err(ctx, EDM_E_ARG, "C must be in 1..64");
+  if (B < 0 || L < 1 || ldx < L) return set_err(ctx, EDM_E_ARG, "need B >= 0, L >= 1, ldx >= L");
+  if (B > 65535) return set_err(ctx, EDM_E_ARG, "at most 65535 series per call");
+  return EDM_OK;
+}
+
+int net_ws(edm_ctx *ctx, int32_t C, int64_t B, int64_t L) {
+  const size_t bytes = sizeof(float) * static_cast<size_t>(edm::net_workspace_floats(C, B, L));
+  if (bytes > workspace_limit()) return set_err(ctx, EDM_E_NOMEM, "network workspace exceeds EDM_WORKSPACE_LIMIT: use smaller batches");
+  return ws_reserve(ctx, bytes);
+}
+}  // namespace
+
+int edm_net_forward(edm_ctx *ctx, const float *params, int32_t C, const float *X, int64_t B,
+                    int64_t L, int64_t ldx, float *logits) {
+  EDM_RC(check_net(ctx, params, C, X, B, L, ldx));
+  if (B > 0 && !logits) return set_err(ctx, EDM_E_ARG, "NULL logits");
+  EDM_RC(check_ctx(ctx));
+  if (B == 0) return EDM_OK;
+  EDM_RC(net_ws(ctx, C, B, L));
+  EDM_HIP(ctx, edm::net_forward(params, C, X, B, L, ldx, reinterpret_cast<float *>(ctx->ws), logits, ctx->stream));
+  return EDM_OK;
+}
+
+int edm_net_loss_grad(edm_ctx *ctx, const float *params, int32_t C, const float *X,
+                      const int32_t *labels, int64_t B, int64_t L, int64_t ldx, float *loss,
+                      float *grad) {
+  EDM_RC(check_net(ctx, params, C, X, B, L, ldx));
+  if (B < 1 || !labels || !loss || !grad) return set_err(ctx, EDM_E_ARG, "need B >= 1 and labels, loss, grad");
+  EDM_RC(check_ctx(ctx));
+  EDM_RC(net_ws(ctx, C, B, L));
+  EDM_HIP(ctx, edm::net_loss_grad(params, C, X, labels, B, L, ldx, reinterpret_cast<float *>(ctx->ws), loss, grad, ctx->stream));
+  return EDM_OK;
+}
+
+int edm_net_adam(edm_ctx *ctx, float *params, const float *grad, float *m, float *v, int64_t n,
+                 int32_t step, float lr, float beta1, float beta2, float eps) {
+  if (!params || !grad || !m || !v) return set_err(ctx, EDM_E_ARG, "NULL pointer");
+  if (n < 0 || step < 1) return set_err(ctx, EDM_E_ARG, "need n >= 0 and step >= 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps >= 0.0f))
+    return set_err(ctx, EDM_E_ARG, "need 0 <= beta < 1 and eps >= 0");
+  EDM_RC(check_ctx(ctx));
+  if (n == 0) return EDM_OK;
+  EDM_HIP(ctx, edm::net_adam(params, grad, m, v, n, step, lr, beta1, beta2, eps, ctx->stream));
+  return EDM_OK;
+}
+
+int edm_select_E(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int64_t ldx,
+                 int32_t E_max, int32_t tau, int32_t Tp, const float *logits, int32_t m_top,
+                 float min_conf, float *rho, int32_t *E_opt, int64_t *n_fallback) {
+  std::string msg;
+  const int rc = edm::check_sweep(X, L, N, ldx, E_max, tau, Tp, rho, E_opt, msg);
+  if (rc != EDM_OK) return set_err(ctx, rc, msg);
+  if (N > 0 && !logits) return set_err(ctx, EDM_E_ARG, "NULL logits");
+  if (m_top < 1 || m_top > EDM_NET_CLASSES) return set_err(ctx, EDM_E_ARG, "m_top must be in 1..20");
+  if (!(min_conf >= 0.0f && min_conf <= 1.0f)) return set_err(ctx, EDM_E_ARG, "min_conf must be in [0, 1]");
+  EDM_RC(check_ctx(ctx));
+  if (n_fallback) *n_fallback = 0;
+  if (N == 0) return EDM_OK;
+  if (N > INT32_MAX) return set_err(ctx, EDM_E_ARG, "too many series");
+  const int64_t L_max = *std::max_element(L, L + N);
+  const int32_t mom_blocks = static_cast<int32_t>((L_max + edm::kKnnThreads - 1) / edm::kKnnThreads);
+  Plan plan;
+  const size_t off_L = plan.take(sizeof(int64_t) * N);
+  const size_t off_ids = plan.take(sizeof(int32_t) * static_cast<size_t>(N) * E_max);
+  const size_t off_cand = plan.take(sizeof(uint32_t) * N);
+  const size_t off_mom = plan.take(edm::kMomBytes * static_cast<size_t>(N) * E_max * mom_blocks);
+  if (plan.bytes > workspace_limit()) return set_err(ctx, EDM_E_NOMEM, "selection workspace exceeds EDM_WORKSPACE_LIMIT");
+  EDM_RC(ws_reserve(ctx, plan.bytes));
+  int64_t *L_dev = reinterpret_cast<int64_t *>(ctx->ws + off_L);
+  int32_t *ids_dev = reinterpret_cast<int32_t *>(ctx->ws + off_ids);
+  uint32_t *cand = reinterpret_cast<uint32_t *>(ctx->ws + off_cand);
+  edm::Mom *mom = reinterpret_cast<edm::Mom *>(ctx->ws + off_mom);
+  EDM_RC(upload(ctx, L, sizeof(int64_t) * N, L_dev));
+  EDM_HIP(ctx, edm::launch_candidates(logits, N, E_max, m_top, min_conf, cand, ctx->stream));
+  std::vector<uint32_t> ch(static_cast<size_t>(N));
+  EDM_HIP(ctx, hipMemcpyAsync(ch.data(), cand, sizeof(uint32_t) * N, hipMemcpyDeviceToHost, ctx->stream));
+  EDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const uint32_t all = (E_max >= 32) ? 0xffffffffu : ((1u << E_max) - 1u);
+  std::vector<int32_t> ids;
+  ids.reserve(static_cast<size_t>(N) * 2);
+  std::vector<int64_t> at(E_max + 2, 0);
+  int64_t fb = 0;
+  for (int64_t s = 0; s < N; ++s) fb += (ch[static_cast<size_t>(s)] == all && m_top < E_max);
+  for (int E = 1; E <= E_max; ++E) {
+    at[E] = static_cast<int64_t>(ids.size());
+    for (int64_t s = 0; s < N; ++s) {
+      const int64_t m = L[s] - static_cast<int64_t>(E - 1) * tau - Tp;
+      if (((ch[static_cast<size_t>(s)] >> (E - 1)) & 1u) && m - 1 >= E + 1) ids.push_back(static_cast<int32_t>(s));
+    }
+  }
+  at[E_max + 1] = static_cast<int64_t>(ids.size());
+  if (!ids.empty()) EDM_RC(upload(ctx, ids.data(), sizeof(int32_t) * ids.size(), ids_dev));
+  for (int E = 1; E <= E_max; ++E) {
+    const int64_t n_E = at[E + 1] - at[E];
+    if (n_E == 0) continue;
+    edm::KnnArgs a{};
+    a.X = X;
+    a.ldx = ldx;
+    a.L_dev = L_dev;
+    a.lib_ids = ids_dev + at[E];
+    a.E = E;
+    a.tau = tau;
+    a.Tp = Tp;
+    a.k = E + 1;
+    a.mom = mom;
+    a.mom_blocks = mom_blocks;
+    a.E_max = E_max;
+    a.status = ctx->status;
+    EDM_HIP(ctx, edm::launch_knn(a, static_cast<int>(n_E), L_max, ctx->stream));
+  }
+  EDM_HIP(ctx, edm::launch_sweep_finalize(mom, mom_blocks, L_dev, N, E_max, tau, Tp, cand, rho, E_opt, ctx->stream));
+  if (n_fallback) *n_fallback = fb;
   return EDM_OK;
 }
 

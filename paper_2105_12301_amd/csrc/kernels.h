@@ -67,9 +67,13 @@ hipError_t launch_lookup(const LookupArgs &a, int nslots, int64_t m_max, hipStre
 
 // Sweep epilogue: merge the per-block moments into rho[N][E_max] and pick
 // E_opt (smallest E with the largest non-NaN rho).
+// cand: optional per-series bit set of the E values evaluated (nullptr: all).
 hipError_t launch_sweep_finalize(const Mom *mom, int32_t mom_blocks, const int64_t *L_dev,
-                                 int64_t N, int32_t E_max, int32_t tau, int32_t Tp, float *rho,
-                                 int32_t *E_opt, hipStream_t st);
+                                 int64_t N, int32_t E_max, int32_t tau, int32_t Tp,
+                                 const uint32_t *cand, float *rho, int32_t *E_opt,
+                                 hipStream_t st);
+hipError_t launch_candidates(const float *logits, int64_t N, int32_t E_max, int32_t m_top,
+                             float min_conf, uint32_t *cand, hipStream_t st);
 
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
 hipError_t launch_embed(const float *x, int64_t L, int32_t E, int32_t tau, float *out,

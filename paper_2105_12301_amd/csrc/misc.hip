@@ -12,8 +12,8 @@ namespace {
 // float64 correlation before it is rounded for output.
 __global__ void k_sweep_finalize(const Mom *__restrict__ mom, int32_t mom_blocks,
                                  const int64_t *__restrict__ L, int64_t N, int32_t E_max,
-                                 int32_t tau, int32_t Tp, float *__restrict__ rho,
-                                 int32_t *__restrict__ E_opt) {
+                                 int32_t tau, int32_t Tp, const uint32_t *__restrict__ cand,
+                                 float *__restrict__ rho, int32_t *__restrict__ E_opt) {
   const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= N) return;
   double best = -__builtin_inf();
@@ -21,7 +21,8 @@ __global__ void k_sweep_finalize(const Mom *__restrict__ mom, int32_t mom_blocks
   for (int E = 1; E <= E_max; ++E) {
     const int64_t m = L[s] - static_cast<int64_t>(E - 1) * tau - Tp;
     double r = __builtin_nan("");
-    if (m - 1 >= E + 1) {
+    const bool evaluated = cand == nullptr || ((cand[s] >> (E - 1)) & 1u);
+    if (evaluated && m - 1 >= E + 1) {
       const int nb = static_cast<int>((m + kKnnThreads - 1) / kKnnThreads);
       const Mom *base = mom + (s * E_max + (E - 1)) * static_cast<int64_t>(mom_blocks);
       Mom t = base[0];
@@ -35,6 +36,34 @@ __global__ void k_sweep_finalize(const Mom *__restrict__ mom, int32_t mom_blocks
     }
   }
   E_opt[s] = best_e;
+}
+
+// Candidate E set of each series from the network's logits: the m_top
+// largest classes (ties to the smaller E), or every E when the largest
+// softmax probability is below min_conf.  Bit E-1 of cand[s] marks E.
+__global__ void k_candidates(const float *__restrict__ logits, int64_t N, int32_t E_max,
+                             int32_t m_top, float min_conf, uint32_t *__restrict__ cand) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  const float *z = logits + s * EDM_NET_CLASSES;
+  float mx = z[0];
+  for (int j = 1; j < EDM_NET_CLASSES; ++j) mx = fmaxf(mx, z[j]);
+  float sum = 0.0f;
+  for (int j = 0; j < EDM_NET_CLASSES; ++j) sum += expf(z[j] - mx);
+  const uint32_t all = E_max >= 32 ? 0xffffffffu : ((1u << E_max) - 1u);
+  if (1.0f / sum < min_conf) {
+    cand[s] = all;
+    return;
+  }
+  uint32_t m = 0;
+  for (int r = 0; r < m_top; ++r) {
+    int best = -1;
+    for (int j = 0; j < EDM_NET_CLASSES; ++j)
+      if (!((m >> j) & 1u) && (best < 0 || z[j] > z[best])) best = j;
+    m |= 1u << best;
+  }
+  m &= all;
+  cand[s] = m ? m : all;
 }
 
 __global__ void k_fill(float *__restrict__ p, int64_t n, float v) {
@@ -69,11 +98,20 @@ unsigned grid_for(int64_t n, int threads) {
 }  // namespace
 
 hipError_t launch_sweep_finalize(const Mom *mom, int32_t mom_blocks, const int64_t *L_dev,
-                                 int64_t N, int32_t E_max, int32_t tau, int32_t Tp, float *rho,
-                                 int32_t *E_opt, hipStream_t st) {
+                                 int64_t N, int32_t E_max, int32_t tau, int32_t Tp,
+                                 const uint32_t *cand, float *rho, int32_t *E_opt,
+                                 hipStream_t st) {
   if (N <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_sweep_finalize, dim3(grid_for(N, 64)), dim3(64), 0, st, mom, mom_blocks,
-                     L_dev, N, E_max, tau, Tp, rho, E_opt);
+                     L_dev, N, E_max, tau, Tp, cand, rho, E_opt);
+  return hipGetLastError();
+}
+
+hipError_t launch_candidates(const float *logits, int64_t N, int32_t E_max, int32_t m_top,
+                             float min_conf, uint32_t *cand, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_candidates, dim3(grid_for(N, 64)), dim3(64), 0, st, logits, N, E_max,
+                     m_top, min_conf, cand);
   return hipGetLastError();
 }
 

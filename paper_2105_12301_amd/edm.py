@@ -33,10 +33,16 @@ E_MAX = 20
 K_MAX = 32
 L_MAX = 32768
 
+NET_KW = 7
+NET_CLASSES = 20
+NET_C_MAX = 64
+
 EXPORTS = (
     "edm_ctx_create", "edm_ctx_set_form", "edm_sync", "edm_last_error",
     "edm_ctx_destroy", "edm_embed", "edm_knn", "edm_lookup",
     "edm_simplex_sweep", "edm_ccm",
+    "edm_net_param_count", "edm_net_forward", "edm_net_loss_grad", "edm_net_adam",
+    "edm_select_E",
 )
 
 
@@ -75,8 +81,16 @@ def load_library(path: str = LIB_PATH):
         lib.edm_lookup.argtypes = [_p, _p, _p, _i64, _i32, _i32, _i32, _i32, _p, _i64, _i64, _p, _p]
         lib.edm_simplex_sweep.argtypes = [_p, _p, _p, _i64, _i64, _i32, _i32, _i32, _p, _p]
         lib.edm_ccm.argtypes = [_p, _p, _p, _i64, _i64, _p, _p, _i64, _i64, _p, _i32, _i32, _p]
+        lib.edm_net_param_count.argtypes = [_i32]
+        lib.edm_net_param_count.restype = _i64
+        lib.edm_net_forward.argtypes = [_p, _p, _i32, _p, _i64, _i64, _i64, _p]
+        lib.edm_net_loss_grad.argtypes = [_p, _p, _i32, _p, _p, _i64, _i64, _i64, _p, _p]
+        lib.edm_net_adam.argtypes = [_p, _p, _p, _p, _p, _i64, _i32, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float, ctypes.c_float]
+        lib.edm_select_E.argtypes = [_p, _p, _p, _i64, _i64, _i32, _i32, _i32, _p, _i32,
+                                     ctypes.c_float, _p, _p, ctypes.POINTER(_i64)]
         for name in EXPORTS:
-            if name not in ("edm_last_error", "edm_ctx_destroy"):
+            if name not in ("edm_last_error", "edm_ctx_destroy", "edm_net_param_count"):
                 getattr(lib, name).restype = ctypes.c_int
         _lib = lib
         return lib
@@ -251,3 +265,66 @@ def edm_ccm(X, E_tgt, Y=None, Lx=None, Ly=None, tau: int = 1, Tp: int = 0, rho=N
         _dev_ptr(E_tgt, torch.int32, "E_tgt"), tau, Tp, _dev_ptr(rho, torch.float32, "rho")),
         ctx.handle)
     return rho
+
+
+# ---------------------------------------------------------------- surrogate --
+def edm_net_param_count(C: int) -> int:
+    n = load_library().edm_net_param_count(int(C))
+    if n < 0:
+        raise EdmError(EDM_E_ARG, "C must be in 1..64")
+    return int(n)
+
+
+def edm_net_forward(params, C: int, X, logits=None, ctx: Context | None = None):
+    """logits float32 [B][20] of the surrogate network for series X [B][L]."""
+    ctx = ctx or default_context(X.device)
+    B, L = X.shape
+    if logits is None:
+        logits = torch.empty((B, NET_CLASSES), dtype=torch.float32, device=X.device)
+    _check(load_library().edm_net_forward(ctx.handle, _dev_ptr(params, torch.float32, "params"), C,
+                                          _dev_ptr(X, torch.float32, "X"), B, L, X.stride(0),
+                                          _dev_ptr(logits, torch.float32, "logits")), ctx.handle)
+    return logits
+
+
+def edm_net_loss_grad(params, C: int, X, labels, grad=None, loss=None, ctx: Context | None = None):
+    """(loss float32 [1], grad float32 [P]) of the mean cross-entropy."""
+    ctx = ctx or default_context(X.device)
+    B, L = X.shape
+    if grad is None:
+        grad = torch.empty_like(params)
+    if loss is None:
+        loss = torch.empty((1,), dtype=torch.float32, device=X.device)
+    _check(load_library().edm_net_loss_grad(ctx.handle, _dev_ptr(params, torch.float32, "params"), C,
+                                            _dev_ptr(X, torch.float32, "X"),
+                                            _dev_ptr(labels, torch.int32, "labels"), B, L, X.stride(0),
+                                            _dev_ptr(loss, torch.float32, "loss"),
+                                            _dev_ptr(grad, torch.float32, "grad")), ctx.handle)
+    return loss, grad
+
+
+def edm_net_adam(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
+                 ctx: Context | None = None):
+    ctx = ctx or default_context(params.device)
+    _check(load_library().edm_net_adam(ctx.handle, _dev_ptr(params, torch.float32, "params"),
+                                       _dev_ptr(grad, torch.float32, "grad"),
+                                       _dev_ptr(m, torch.float32, "m"), _dev_ptr(v, torch.float32, "v"),
+                                       params.numel(), int(step), float(lr), float(beta1),
+                                       float(beta2), float(eps)), ctx.handle)
+
+
+def edm_select_E(X, logits, lengths=None, E_max: int = E_MAX, tau: int = 1, Tp: int = 1,
+                 m_top: int = 2, min_conf: float = 0.0, ctx: Context | None = None):
+    """(rho float32 [N][E_max], E_opt int32 [N], n_fallback) from the network's logits."""
+    ctx = ctx or default_context(X.device)
+    N, ldx = X.shape
+    L = _host_i64(np.full(N, ldx) if lengths is None else lengths, N, "lengths")
+    rho = torch.empty((N, E_max), dtype=torch.float32, device=X.device)
+    E_opt = torch.empty((N,), dtype=torch.int32, device=X.device)
+    nfb = ctypes.c_int64(0)
+    _check(load_library().edm_select_E(
+        ctx.handle, _dev_ptr(X, torch.float32, "X"), L.ctypes.data_as(_p), N, ldx, E_max, tau, Tp,
+        _dev_ptr(logits, torch.float32, "logits"), int(m_top), float(min_conf),
+        _dev_ptr(rho, torch.float32, "rho"), _dev_ptr(E_opt, torch.int32, "E_opt"),
+        ctypes.byref(nfb)), ctx.handle)
+    return rho, E_opt, int(nfb.value)

@@ -40,6 +40,7 @@ __all__ = [
     "sine",
     "ramp",
     "tiled_period",
+    "net_init_params",
 ]
 
 
@@ -218,6 +219,25 @@ def surrogate_mix(seed: int = 5, N: int = 50000, L: int = 1500):
         if sel.size:
             X[sel] = zscore(gen(rng, sel.size, L)).astype(np.float32)
     return _finite(X), fam
+
+
+def net_init_params(C: int, seed: int = 0, kw: int = 7, n_class: int = 20) -> np.ndarray:
+    """Random initial parameters of the E surrogate network, flat float32.
+
+    Layout w1[C][1][kw], b1[C], w2[C][C][kw], b2[C], w3[C][C][kw], b3[C],
+    wo[n_class][C], bo[n_class]; weights ~ U(-sqrt(6/fan_in), +sqrt(6/fan_in)),
+    biases zero.
+    """
+    rng = np.random.default_rng(seed)
+    shapes = [(C, 1, kw), (C,), (C, C, kw), (C,), (C, C, kw), (C,), (n_class, C), (n_class,)]
+    parts = []
+    for shp in shapes:
+        if len(shp) == 1:
+            parts.append(np.zeros(shp))
+        else:
+            lim = np.sqrt(6.0 / int(np.prod(shp[1:])))
+            parts.append(rng.uniform(-lim, lim, size=shp))
+    return np.concatenate([q.ravel() for q in parts]).astype(np.float32)
 
 
 # --- closed-form fixtures used by the pins -------------------------------

@@ -17,7 +17,7 @@ P = ctypes.c_void_p(256)  # a non-NULL stand-in; never dereferenced by validatio
 def declared_symbols():
     src = open(os.path.join(ROOT, "include", "edm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(edm_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(edm_[A-Za-z_]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -109,3 +109,24 @@ def test_product_path_never_touches_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle", text, re.M), f
                 assert "oracle" not in text.lower(), f"{f} mentions the oracle"
+
+
+def test_net_validation(lib):
+    assert lib.edm_net_param_count(64) == 7 * 64 + 64 + 2 * (64 * 64 * 7 + 64) + 20 * 64 + 20
+    assert lib.edm_net_param_count(0) < 0 and lib.edm_net_param_count(65) < 0
+    f = lib.edm_net_forward
+    assert f(NULL, P, 0, P, 4, 100, 100, P) == edm.EDM_E_ARG        # C = 0
+    assert f(NULL, P, 8, P, 4, 100, 99, P) == edm.EDM_E_ARG         # ldx < L
+    assert f(NULL, P, 8, P, 4, 100, 100, NULL) == edm.EDM_E_ARG     # no logits
+    assert f(NULL, P, 8, P, 4, 100, 100, P) == edm.EDM_E_ARG        # NULL ctx
+    g = lib.edm_net_loss_grad
+    assert g(NULL, P, 8, P, NULL, 4, 100, 100, P, P) == edm.EDM_E_ARG
+    a = lib.edm_net_adam
+    assert a(NULL, P, P, P, P, 10, 0, 1e-3, 0.9, 0.999, 1e-8) == edm.EDM_E_ARG   # step 0
+    assert a(NULL, P, P, P, P, 10, 1, 1e-3, 1.0, 0.999, 1e-8) == edm.EDM_E_ARG   # beta1 = 1
+    L = (ctypes.c_int64 * 2)(100, 100)
+    s = lib.edm_select_E
+    nfb = ctypes.c_int64()
+    assert s(NULL, P, L, 2, 100, 20, 1, 1, P, 0, 0.0, P, P, ctypes.byref(nfb)) == edm.EDM_E_ARG
+    assert s(NULL, P, L, 2, 100, 20, 1, 1, P, 2, 1.5, P, P, ctypes.byref(nfb)) == edm.EDM_E_ARG
+    assert s(NULL, P, L, 2, 100, 20, 1, 1, NULL, 2, 0.5, P, P, ctypes.byref(nfb)) == edm.EDM_E_ARG

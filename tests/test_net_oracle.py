@@ -1,0 +1,65 @@
+"""Pins for the surrogate-network oracle: finite differences, a library
+convolution, closed forms of the loss and of the first Adam step."""
+import math
+
+import numpy as np
+import pytest
+from scipy.signal import correlate
+
+from oracle import net_oracle as N
+from paper_2105_12301_amd import synth
+
+
+def test_param_count_matches_layout():
+    C = 64
+    assert N.param_count(C) == 7 * C + C + C * C * 7 + C + C * C * 7 + C + 20 * C + 20
+    theta = synth.net_init_params(C, seed=1)
+    assert theta.size == N.param_count(C)
+    p = N.unpack(theta, C)
+    assert p["w2"].shape == (C, C, 7) and np.all(p["b3"] == 0)
+
+
+def test_conv_same_against_scipy_correlate():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(2, 3, 20))
+    w = rng.normal(size=(4, 3, 7))
+    b = rng.normal(size=4)
+    y = N.conv_same(x, w, b)
+    for n in range(2):
+        for o in range(4):
+            ref = b[o] + sum(correlate(x[n, i], w[o, i], mode="same") for i in range(3))
+            np.testing.assert_allclose(y[n, o], ref, rtol=1e-12, atol=1e-12)
+
+
+def test_uniform_logits_loss_is_log20():
+    C = 4
+    theta = np.zeros(N.param_count(C))
+    X = np.random.default_rng(1).normal(size=(5, 30))
+    assert abs(N.loss(theta, X, [1, 5, 20, 3, 7], C) - math.log(20.0)) < 1e-12
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gradients_match_central_differences(seed):
+    C, L, B = 3, 16, 4
+    rng = np.random.default_rng(seed)
+    theta = synth.net_init_params(C, seed=seed).astype(np.float64)
+    theta += rng.normal(scale=0.05, size=theta.size)   # non-zero biases too
+    X = rng.normal(size=(B, L))
+    y = rng.integers(1, 21, size=B)
+    _, g = N.loss_and_grads(theta, X, y, C)
+    h = 1e-6
+    idx = np.unique(np.r_[np.arange(0, theta.size, 7), theta.size - 1, theta.size - 20])
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (N.loss(tp, X, y, C) - N.loss(tm, X, y, C)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 + 1e-5 * abs(fd), (i, fd, g[i])
+
+
+def test_first_adam_step_moves_by_lr_times_sign():
+    rng = np.random.default_rng(2)
+    th = rng.normal(size=50)
+    g = rng.normal(size=50)
+    new, m, v = N.adam_step(th, g, np.zeros(50), np.zeros(50), 1, 1e-3, eps=0.0)
+    np.testing.assert_allclose(new, th - 1e-3 * np.sign(g), rtol=0, atol=1e-15)
