@@ -344,11 +344,22 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
   const size_t off_ids = plan.take(sizeof(int32_t) * Nt);
   const size_t small_bytes = plan.bytes;
   const size_t off_tbl = plan.take(0);
-  size_t per_lib_max = 0;  // table bytes of one library at the largest E in use
+  // Table bytes of one library: the largest E in use (plain form, one E at a
+  // time) or every E in use together (chosen form, one scan per E group).
+  const bool batched = ctx->form == EDM_FORM_CHOSEN && tau == 1;
+  size_t per_lib_max = 0;
+  std::vector<size_t> off_E(EDM_E_MAX + 1, 0);
   for (int e = 1; e <= EDM_E_MAX; ++e) {
     if (bucket[e].empty()) continue;
     const int64_t m = Lx_max - static_cast<int64_t>(e - 1) * tau - Tp;
-    if (m > 0) per_lib_max = std::max(per_lib_max, static_cast<size_t>(m) * (e + 1) * 8);
+    if (m <= 0) continue;
+    const size_t b = align_up(static_cast<size_t>(m) * (e + 1) * 8, 256);
+    if (batched) {
+      off_E[e] = per_lib_max;
+      per_lib_max += b;
+    } else {
+      per_lib_max = std::max(per_lib_max, b);
+    }
   }
   const size_t limit = workspace_limit();
   if (per_lib_max > 0 && off_tbl + per_lib_max > limit)
@@ -375,6 +386,62 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
   const int32_t *ids_dev = reinterpret_cast<const int32_t *>(ctx->ws + off_ids);
 
   EDM_HIP(ctx, edm::launch_fill(rho, Nl * Nt, __builtin_nanf(""), ctx->stream));
+
+  if (batched) {
+    // Chosen form: per library batch, one scan per E group writes the tables
+    // of every E in use, then one lookup launch per E.
+    uint32_t need = 0;
+    for (int e = 1; e <= EDM_E_MAX; ++e) {
+      const int64_t m_max = Lx_max - static_cast<int64_t>(e - 1) - Tp;
+      if (!bucket[e].empty() && m_max - 1 >= e + 1) need |= 1u << (e - 1);
+    }
+    for (int64_t b0 = 0; b0 < Nl && need; b0 += batch) {
+      const int64_t nb = std::min<int64_t>(batch, Nl - b0);
+      const int64_t L_b = *std::max_element(Lx + b0, Lx + b0 + nb);
+      edm::KnnArgs a{};
+      a.X = X + b0 * ldx;
+      a.ldx = ldx;
+      a.L_dev = Lx_dev + b0;
+      a.tau = 1;
+      a.Tp = Tp;
+      a.E_max = EDM_E_MAX;
+      a.status = ctx->status;
+      a.need = need;
+      for (int e = 1; e <= EDM_E_MAX; ++e) {
+        if (!((need >> (e - 1)) & 1u)) continue;
+        const int64_t m_max = Lx_max - static_cast<int64_t>(e - 1) - Tp;
+        const int64_t stride = m_max * (e + 1);
+        char *base = ctx->ws + off_tbl + off_E[e] * static_cast<size_t>(batch);
+        a.idxE[e] = reinterpret_cast<int32_t *>(base);
+        a.wE[e] = reinterpret_cast<float *>(base + sizeof(int32_t) * stride * batch);
+        a.strideE[e] = stride;
+      }
+      EDM_HIP(ctx, edm::launch_sweep_multi(a, static_cast<int>(nb), L_b, ctx->stream));
+      for (int e = 1; e <= EDM_E_MAX; ++e) {
+        if (!((need >> (e - 1)) & 1u)) continue;
+        edm::LookupArgs b{};
+        b.idx = a.idxE[e];
+        b.w = a.wE[e];
+        b.tbl_stride = a.strideE[e];
+        b.Lx_dev = Lx_dev + b0;
+        b.E = e;
+        b.tau = 1;
+        b.Tp = Tp;
+        b.k = e + 1;
+        b.Y = Y;
+        b.ldy = ldy;
+        b.Ly_dev = Ly_dev;
+        b.tgt_ids = ids_dev + bucket_at[e];
+        b.ntgt = static_cast<int32_t>(bucket[e].size());
+        b.rho = rho + b0 * Nt;
+        b.ldrho = Nt;
+        b.status = ctx->status;
+        const int64_t m_b = L_b - static_cast<int64_t>(e - 1) - Tp;
+        EDM_HIP(ctx, edm::launch_lookup(b, static_cast<int>(nb), m_b, ctx->stream));
+      }
+    }
+    return EDM_OK;
+  }
 
   for (int e = 1; e <= EDM_E_MAX; ++e) {
     if (bucket[e].empty()) continue;

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "../../include/edm.h"
+
 namespace edm {
 
 struct Mom;
@@ -31,14 +33,22 @@ struct KnnArgs {
   int32_t mom_blocks;        // blocks per (row, E) in mom
   int32_t E_max;             // sweep: number of E slots per row in mom
   int *status;               // device status word (bit 0: non-finite input)
+  // Batched kernel, table mode: bit E-1 of need marks the E whose tables are
+  // written to idxE[E] / wE[E] ([slot][nq][E+1], slot stride strideE[E]).
+  uint32_t need;
+  int32_t *idxE[EDM_E_MAX + 1];
+  float *wE[EDM_E_MAX + 1];
+  int64_t strideE[EDM_E_MAX + 1];
 };
 
 // Launch the kNN kernel for `nslots` libraries whose longest series has
 // `L_max` samples.  Returns a hipError_t.
 hipError_t launch_knn(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t st);
 
-// Batched E sweep (tau = 1): one scan per group of E values; same outputs
-// (per-block co-moments in a.mom) as one launch_knn per E in sweep mode.
+// Batched kNN (tau = 1): one scan per group of E values.  With a.mom set it
+// writes the sweep's per-block co-moments for E = 1..a.E_max; otherwise it
+// writes the tables of every E marked in a.need.  Outputs are bit-identical to
+// launch_knn per E.
 hipError_t launch_sweep_multi(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t st);
 
 // Arguments of the batched lookup + on-the-fly Pearson kernel.  One

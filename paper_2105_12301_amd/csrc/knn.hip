@@ -101,7 +101,8 @@ __global__ __launch_bounds__(kKnnThreads) void k_knn(KnnArgs a, int slot0) {
   __syncthreads();
 
   const int lane = threadIdx.x & (kWave - 1);
-  const int p0 = blk0 + (threadIdx.x & ~(kWave - 1));
+  // wave-uniform: readfirstlane lets the compiler keep it (and the self step) scalar
+  const int p0 = __builtin_amdgcn_readfirstlane(blk0 + static_cast<int>(threadIdx.x & ~(kWave - 1)));
   const int p = p0 + lane;
   const bool active = p < m;
 

@@ -99,7 +99,8 @@ __global__ __launch_bounds__(kKnnThreads) void k_sweep_multi(KnnArgs a, int slot
   __syncthreads();
 
   const int lane = threadIdx.x & (kWave - 1);
-  const int p0 = blk0 + (threadIdx.x & ~(kWave - 1));
+  // wave-uniform: readfirstlane lets the compiler keep it (and the self step) scalar
+  const int p0 = __builtin_amdgcn_readfirstlane(blk0 + static_cast<int>(threadIdx.x & ~(kWave - 1)));
   const int p = p0 + lane;
 
   float vp[EHI];
@@ -111,7 +112,8 @@ __global__ __launch_bounds__(kKnnThreads) void k_sweep_multi(KnnArgs a, int slot
   static_for<ELO, EHI>([&](auto EC) {
     constexpr int E = decltype(EC)::value;
     constexpr int OFF = list_off<ELO>(E);
-    const bool act = p < L - (E - 1) - Tp;
+    // table mode: lists of E that are not needed stay idle (kth = -1)
+    const bool act = p < L - (E - 1) - Tp && (a.mom != nullptr || ((a.need >> (E - 1)) & 1u));
 #pragma unroll
     for (int i = 0; i < E + 1; ++i) {
       qk[OFF + i] = act ? __builtin_inff() : -1.0f;
@@ -161,18 +163,23 @@ __global__ __launch_bounds__(kKnnThreads) void k_sweep_multi(KnnArgs a, int slot
             acc = acc + d * d;
             if constexpr (j + 1 >= ELO) key[j + 1 - ELO] = acc;
           });
-          // One wave-uniform branch for the whole group: the common step
-          // improves no list at all.
-          uint64_t any = 0;
-          static_for<ELO, EHI>([&](auto EC) {
-            constexpr int E = decltype(EC)::value;
-            any |= __builtin_amdgcn_ballot_w64(notself && key[E - ELO] < qk[list_off<ELO>(E) + E]);
-          });
-          if (any) {
-            static_for<ELO, EHI>([&](auto EC) {
+          // One wave-uniform test for the whole group: some list improves iff
+          // min over E of (key_E - kth_E) < 0 in some lane.  For finite keys
+          // the sign of the float32 difference is exact; an empty list
+          // (kth = +inf) gives -inf and an idle one (kth = -1) a positive
+          // value.  The common step improves no list at all.
+          if (notself) {
+            float dm = key[0] - qk[list_off<ELO>(ELO) + ELO];
+            static_for<ELO + 1, EHI>([&](auto EC) {
               constexpr int E = decltype(EC)::value;
-              slice_offer<list_off<ELO>(E), E + 1, TOT>(qk, qi, key[E - ELO], q, notself);
+              dm = fminf(dm, key[E - ELO] - qk[list_off<ELO>(E) + E]);
             });
+            if (__builtin_amdgcn_ballot_w64(dm < 0.0f)) {
+              static_for<ELO, EHI>([&](auto EC) {
+                constexpr int E = decltype(EC)::value;
+                slice_offer<list_off<ELO>(E), E + 1, TOT>(qk, qi, key[E - ELO], q, true);
+              });
+            }
           }
         }
 #pragma unroll
@@ -192,7 +199,8 @@ __global__ __launch_bounds__(kKnnThreads) void k_sweep_multi(KnnArgs a, int slot
     constexpr int OFF = list_off<ELO>(E);
     const int mE = L - (E - 1) - Tp;
     Mom mine = mom_zero();
-    if (p < mE && mE - 1 >= K) {
+    const bool want_table = a.mom == nullptr && ((a.need >> (E - 1)) & 1u);
+    if (p < mE && mE - 1 >= K && (a.mom != nullptr || want_table)) {
       double D[K];
       double dmin = __builtin_inf();
 #pragma unroll 1
@@ -225,17 +233,29 @@ __global__ __launch_bounds__(kKnnThreads) void k_sweep_multi(KnnArgs a, int slot
         D[K - 1] = wq;
       }
       const double inv = 1.0 / wsum;
-      const int o_off = (E - 1) + Tp;
-      double yh = 0.0;
+      if (want_table) {
+        const int64_t base = static_cast<int64_t>(row) * a.strideE[E] + static_cast<int64_t>(p) * K;
 #pragma unroll
-      for (int i = 0; i < K; ++i) yh += (D[i] * inv) * static_cast<double>(xs[qi[OFF + i] + o_off]);
-      mine.n = 1.0;
-      mine.mo = static_cast<double>(xs[p + o_off]);
-      mine.mp = yh;
+        for (int i = 0; i < K; ++i) {
+          a.idxE[E][base + i] = qi[OFF + i];
+          a.wE[E][base + i] = static_cast<float>(D[i] * inv);
+        }
+      } else {
+        const int o_off = (E - 1) + Tp;
+        double yh = 0.0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) yh += (D[i] * inv) * static_cast<double>(xs[qi[OFF + i] + o_off]);
+        mine.n = 1.0;
+        mine.mo = static_cast<double>(xs[p + o_off]);
+        mine.mp = yh;
+      }
     }
-    const Mom wv = mom_wave_reduce(mine);
-    if (lane == 0) wmom[wave][E - ELO] = wv;
+    if (a.mom) {  // uniform
+      const Mom wv = mom_wave_reduce(mine);
+      if (lane == 0) wmom[wave][E - ELO] = wv;
+    }
   });
+  if (a.mom == nullptr) return;
   __syncthreads();
   if (static_cast<int>(threadIdx.x) < NG) {
     const int E = ELO + static_cast<int>(threadIdx.x);
@@ -286,7 +306,13 @@ hipError_t launch_sweep_multi(const KnnArgs &a, int nslots, int64_t L_max, hipSt
   const size_t shm = static_cast<size_t>(L_max) * sizeof(float);
   for (const auto &g : kGroups) {
     const int lo = g[0];
-    const int hi = g[1] < a.E_max ? g[1] : a.E_max;
+    int hi = g[1] < a.E_max ? g[1] : a.E_max;
+    if (a.mom == nullptr) {  // table mode: the group's scan must reach its largest needed E
+      hi = 0;
+      for (int E = lo; E <= g[1]; ++E)
+        if ((a.need >> (E - 1)) & 1u) hi = E;
+      if (hi == 0) continue;
+    }
     if (lo > hi) break;
     const std::array<LaunchFn, 8> &t = lo == 1 ? t1 : lo == 9 ? t9 : lo == 13 ? t13 : lo == 16 ? t16 : t19;
     LaunchFn fn = t[hi - lo];

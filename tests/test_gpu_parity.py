@@ -307,3 +307,23 @@ def test_ccm_chosen_form_matches_oracle(edm, ctx_chosen):
     ctx_chosen.sync()
     ro = O.ccm(X, np.full(N, L), X, np.full(N, L), Eg.cpu().numpy())
     assert np.nanmax(np.abs(rho.cpu().numpy() - ro)) <= RHO_TOL
+
+
+@pytest.mark.parametrize("limit", [None, 3 << 20])
+def test_ccm_batched_tables_bit_identical_to_plain(edm, ctx, ctx_chosen, limit, monkeypatch):
+    # Chosen-form CCM builds every needed E's table in one scan per E group;
+    # the result must equal the plain form bit for bit, also when a small
+    # workspace limit splits the libraries into several batches.
+    if limit:
+        monkeypatch.setenv("EDM_WORKSPACE_LIMIT", str(limit))
+    X, lens, E = synth.spike_trains(seed=9, N=40, L_min=200, L_max=900)
+    Xd, Ed = dev(X), dev(E)
+    rp = edm.edm_ccm(Xd, Ed, Lx=lens, Ly=lens, ctx=ctx)
+    rc = edm.edm_ccm(Xd, Ed, Lx=lens, Ly=lens, ctx=ctx_chosen)
+    ctx.sync()
+    ctx_chosen.sync()
+    assert torch.equal(rp.view(torch.int32), rc.view(torch.int32))
+    ro = O.ccm(X, lens, X, lens, E, lib_rows=[0, 17])
+    g = rc.cpu().numpy()[[0, 17]]
+    assert np.array_equal(np.isnan(g), np.isnan(ro))
+    assert np.nanmax(np.abs(g - ro)) <= RHO_TOL
