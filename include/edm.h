@@ -160,6 +160,46 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl,
             float *rho);
 
 /* ---------------------------------------------------------------------------
+ * Batched CCM plan: libraries of uneven length and targets of uneven E in
+ * one graph of persistent launches (Section 3.4's grouping by E, batched over
+ * libraries).  The plan is built once from the host lengths and E values:
+ * libraries are ordered longest first and split into batches that fit the
+ * workspace limit; per batch, one persistent kernel per E group builds every
+ * table the library's targets need (one candidate scan per group, as the
+ * chosen form of edm_ccm) and one persistent kernel per E runs the lookups.
+ * Work items are pulled from device counters, longest first.  The whole
+ * sequence is captured into a HIP graph on the first edm_ccm_plan_run and
+ * replayed afterwards (re-captured when the buffers change; a context on the
+ * legacy default stream enqueues the launches directly instead, since that
+ * stream cannot be captured).  Results equal edm_ccm bit for bit.  tau = 1.
+ * ------------------------------------------------------------------------- */
+typedef struct edm_plan edm_plan;
+
+/* Launch shapes of a plan (chosen by an autotuner; see edm_tune_default). */
+typedef struct {
+  int32_t tables_wg_per_cu;   /* 0: one workgroup per table item; >0: persistent workgroups per CU */
+  int32_t lookup_wg_per_cu;   /* 0: one workgroup per lookup item; >0: persistent workgroups per CU */
+  int32_t lookup_targets;     /* targets staged per lookup workgroup, 1..4 */
+} edm_tune;
+
+void edm_tune_default(edm_tune *tune);
+
+/* Build a plan.  Lx (host) int64 [Nl], Ly (host) int64 [Nt], E_tgt (host)
+ * int32 [Nt] in 0..20 (0: no E, the column stays NaN); ldx, ldy the row
+ * strides the run will use; tune may be NULL (defaults).  Allocates the
+ * plan's device memory (work lists, offsets, one batch of tables). */
+int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx,
+                        const int64_t *Ly, int64_t Nt, int64_t ldy, const int32_t *E_tgt,
+                        int32_t Tp, const edm_tune *tune, edm_plan **plan);
+
+/* Run (replay) the plan on X [Nl][ldx], Y [Nt][ldy] into rho [Nl][Nt], with
+ * the same definition of defined pairs as edm_ccm. */
+int edm_ccm_plan_run(edm_ctx *ctx, edm_plan *plan, const float *X, const float *Y, float *rho);
+
+/* Release the plan (waits for the context's stream first if ctx != NULL). */
+void edm_ccm_plan_destroy(edm_ctx *ctx, edm_plan *plan);
+
+/* ---------------------------------------------------------------------------
  * Learned embedding-dimension surrogate.
  *
  * A small 1-D convolutional network predicts a series' optimal E from the

@@ -1,0 +1,60 @@
+// Private host-side helpers shared by the libedm host files: the context
+// structure, error reporting, the workspace and the pinned staging buffer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <string>
+
+#include "../../include/edm.h"
+
+struct edm_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int form = EDM_FORM_PLAIN;
+  std::string err;
+  char *ws = nullptr;          // device workspace
+  size_t ws_bytes = 0;
+  int *status = nullptr;       // device status word
+  char *pinned = nullptr;      // host staging buffer
+  size_t pinned_bytes = 0;
+  hipEvent_t pinned_ready = nullptr;  // recorded after the last copy out of `pinned`
+  bool pinned_pending = false;
+};
+
+namespace edm {
+namespace host {
+
+int set_err(edm_ctx *ctx, int code, const std::string &msg);
+int hip_err(edm_ctx *ctx, hipError_t e, const char *what);
+size_t align_up(size_t v, size_t a);
+size_t workspace_limit();
+int ws_reserve(edm_ctx *ctx, size_t bytes);
+int upload(edm_ctx *ctx, const void *host, size_t bytes, void *dev);
+int check_ctx(edm_ctx *ctx);
+
+// Sub-allocation plan inside a buffer.
+struct Plan {
+  size_t bytes = 0;
+  size_t take(size_t n) {
+    const size_t at = align_up(bytes, 256);
+    bytes = at + n;
+    return at;
+  }
+};
+
+}  // namespace host
+}  // namespace edm
+
+#define EDM_HIP(ctx, call)                                            \
+  do {                                                                \
+    hipError_t e_ = (call);                                           \
+    if (e_ != hipSuccess) return ::edm::host::hip_err(ctx, e_, #call); \
+  } while (0)
+
+#define EDM_RC(expr)               \
+  do {                             \
+    const int rc_ = (expr);        \
+    if (rc_ != EDM_OK) return rc_; \
+  } while (0)

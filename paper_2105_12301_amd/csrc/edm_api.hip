@@ -15,27 +15,17 @@
 #include <vector>
 
 #include "../../include/edm.h"
+#include "ctx.h"
 #include "kernels.h"
 #include "net_kernels.h"
 #include "validate.h"
 
-struct edm_ctx {
-  hipStream_t stream = nullptr;
-  int device = 0;
-  int form = EDM_FORM_PLAIN;
-  std::string err;
-  char *ws = nullptr;          // device workspace
-  size_t ws_bytes = 0;
-  int *status = nullptr;       // device status word
-  char *pinned = nullptr;      // host staging buffer
-  size_t pinned_bytes = 0;
-  hipEvent_t pinned_ready = nullptr;  // recorded after the last copy out of `pinned`
-  bool pinned_pending = false;
-};
-
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace edm {
+namespace host {
 
 int set_err(edm_ctx *ctx, int code, const std::string &msg) {
   g_err = msg;
@@ -47,11 +37,6 @@ int hip_err(edm_ctx *ctx, hipError_t e, const char *what) {
   return set_err(ctx, EDM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define EDM_HIP(ctx, call)                              \
-  do {                                                  \
-    hipError_t e_ = (call);                             \
-    if (e_ != hipSuccess) return hip_err(ctx, e_, #call); \
-  } while (0)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -85,15 +70,6 @@ int ws_reserve(edm_ctx *ctx, size_t bytes) {
   return EDM_OK;
 }
 
-// Sub-allocation plan inside the workspace.
-struct Plan {
-  size_t bytes = 0;
-  size_t take(size_t n) {
-    const size_t at = align_up(bytes, 256);
-    bytes = at + n;
-    return at;
-  }
-};
 
 // Host blob -> device copy through the pinned staging buffer.
 int upload(edm_ctx *ctx, const void *host, size_t bytes, void *dev) {
@@ -126,13 +102,11 @@ int check_ctx(edm_ctx *ctx) {
   return EDM_OK;
 }
 
-#define EDM_RC(expr)            \
-  do {                          \
-    const int rc_ = (expr);     \
-    if (rc_ != EDM_OK) return rc_; \
-  } while (0)
 
-}  // namespace
+}  // namespace host
+}  // namespace edm
+
+using namespace edm::host;
 
 extern "C" {
 

@@ -39,7 +39,38 @@ struct KnnArgs {
   int32_t *idxE[EDM_E_MAX + 1];
   float *wE[EDM_E_MAX + 1];
   int64_t strideE[EDM_E_MAX + 1];
+  // Plan mode (persistent kernel): per-row need masks and table offsets
+  // (elements, [row][EDM_E_MAX + 1]) into tbl_idx / tbl_w.
+  const uint32_t *need_dev;
+  const int64_t *tbl_off;
+  int32_t *tbl_idx;
+  float *tbl_w;
 };
+
+// Work item of the persistent table kernel: E group and query block of a row.
+struct TableItem {
+  int32_t row;
+  int16_t group;
+  int16_t blk;
+};
+
+// Work item of the persistent lookup kernel: a tile of targets of one E for
+// one library (targets bucket_ids[bucket_at[E] + tile*T ...]).
+constexpr int kLookupItemMaxTargets = 4;  // T of a LookupItem is at most this
+struct LookupItem {
+  int32_t lib;
+  int16_t E;
+  int16_t T;
+  int32_t first;  // index of the tile's first target inside the E bucket
+  int32_t count;  // targets in this tile
+};
+
+// Persistent table kernel of one E group (0: E 1-8, 1: 9-12, 2: 13-15,
+// 3: 16-18, 4: 19-20) over its work list (counter: a device int that starts
+// at 0).
+hipError_t launch_tables_persistent(const KnnArgs &a, int group, const TableItem *items,
+                                    int n_items, int *counter, int64_t L_max, int wg_per_cu,
+                                    int n_cu, hipStream_t st);
 
 // Launch the kNN kernel for `nslots` libraries whose longest series has
 // `L_max` samples.  Returns a hipError_t.
@@ -71,7 +102,22 @@ struct LookupArgs {
   float *pred;               // pred[tgt*ldpred + p] (single table only) or nullptr
   int64_t ldpred;
   int *status;
+  // Plan mode (item kernels): tables at tbl_off[lib][E] in tbl_idx / tbl_w,
+  // targets of E listed at bucket_ids[bucket_at[E] ...].
+  const int64_t *tbl_off;
+  const int32_t *tbl_idx;
+  const float *tbl_w;
+  const int32_t *bucket_ids;
+  const int32_t *bucket_at;
 };
+
+// Lookups of the work list of one E: persistent (wg_per_cu * n_cu
+// workgroups pulling items from *counter) or one workgroup per item
+// (wg_per_cu = 0).
+// lds_floats: dynamic LDS per workgroup (max over items of T * m).
+hipError_t launch_lookup_items(const LookupArgs &a, int E, const LookupItem *items, int n_items,
+                               int *counter, int64_t lds_floats, int wg_per_cu, int n_cu,
+                               hipStream_t st);
 
 hipError_t launch_lookup(const LookupArgs &a, int nslots, int64_t m_max, hipStream_t st);
 

@@ -20,21 +20,24 @@ namespace edm {
 namespace {
 
 constexpr int kTMax = 8;               // targets per workgroup, upper bound
+constexpr int kItemTMax = 4;           // the same for work-list items (register budget)
 constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS for staged targets
 
-template <int K>
-__global__ __launch_bounds__(kLookupThreads) void k_lookup(LookupArgs a, int T, int slot0) {
-  extern __shared__ float ys[];  // [T][m]
+// One workgroup's lookups: library `lib` with table (idx, w) [nq][K] at
+// dimension E, targets tgt_ids[t0 .. t0+T) of a list of ntgt (identity list
+// when tgt_ids is null).  Every early return is uniform across the workgroup.
+template <int K, int kTMax>
+__device__ __forceinline__ void lookup_body(const LookupArgs &a, const int E, const int lib,
+                                            const int32_t *__restrict__ tidx,
+                                            const float *__restrict__ tw,
+                                            const int32_t *__restrict__ tgt_ids, const int t0,
+                                            const int T, const int ntgt, float *__restrict__ ys) {
   __shared__ Mom wmom[kLookupThreads / kWave][kTMax];
-
-  const int slot = slot0 + static_cast<int>(blockIdx.y);
-  const int lib = a.lib_ids ? a.lib_ids[slot] : slot;
   const int64_t Lx = a.Lx_dev ? a.Lx_dev[lib] : a.Lx_uni;
-  const int off = (a.E - 1) * a.tau + a.Tp;
+  const int off = (E - 1) * a.tau + a.Tp;
   const int m = static_cast<int>(Lx) - off;
   if (m - 1 < K) return;  // the table does not exist for this library
-  const int t0 = static_cast<int>(blockIdx.x) * T;
-  if (t0 >= a.ntgt) return;
+  if (t0 >= ntgt) return;
 
   int tgt[kTMax];
   bool ok[kTMax];
@@ -42,8 +45,8 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup(LookupArgs a, int T, 
 #pragma unroll
   for (int t = 0; t < kTMax; ++t) {
     const int jt = t0 + t;
-    ok[t] = t < T && jt < a.ntgt;
-    tgt[t] = ok[t] ? (a.tgt_ids ? a.tgt_ids[jt] : jt) : 0;
+    ok[t] = t < T && jt < ntgt;
+    tgt[t] = ok[t] ? (tgt_ids ? tgt_ids[jt] : jt) : 0;
     if (ok[t] && a.Ly_dev && a.Ly_dev[tgt[t]] < Lx) ok[t] = false;  // pair undefined
     if (ok[t]) {
       const float *__restrict__ y = a.Y + static_cast<int64_t>(tgt[t]) * a.ldy + off;
@@ -62,15 +65,14 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup(LookupArgs a, int T, 
 #pragma unroll
   for (int t = 0; t < kTMax; ++t) ro[t] = rp[t] = so[t] = sp[t] = soo[t] = spp[t] = sop[t] = 0.0;
 
-  const int64_t tbl = static_cast<int64_t>(slot) * a.tbl_stride;
   for (int p = threadIdx.x; p < m; p += kLookupThreads) {
     int qi[K];
     float wi[K];
-    const int64_t row = tbl + static_cast<int64_t>(p) * K;
+    const int64_t row = static_cast<int64_t>(p) * K;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      qi[i] = a.idx[row + i];
-      wi[i] = a.w[row + i];
+      qi[i] = tidx[row + i];
+      wi[i] = tw[row + i];
     }
 #pragma unroll
     for (int t = 0; t < kTMax; ++t) {
@@ -116,14 +118,65 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup(LookupArgs a, int T, 
   if (a.rho && static_cast<int>(threadIdx.x) < T) {
     const int t = threadIdx.x;
     const int jt = t0 + t;
-    if (jt < a.ntgt) {
+    if (jt < ntgt) {
       Mom s = wmom[0][t];
 #pragma unroll
       for (int w = 1; w < kLookupThreads / kWave; ++w) s = mom_merge(s, wmom[w][t]);
-      const int j = a.tgt_ids ? a.tgt_ids[jt] : jt;
+      const int j = tgt_ids ? tgt_ids[jt] : jt;
       const bool defined = !(a.Ly_dev && a.Ly_dev[j] < Lx);
       if (defined) a.rho[static_cast<int64_t>(lib) * a.ldrho + j] = static_cast<float>(mom_rho(s));
     }
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kLookupThreads) void k_lookup(LookupArgs a, int T, int slot0) {
+  extern __shared__ float ys[];  // [T][m]
+  const int slot = slot0 + static_cast<int>(blockIdx.y);
+  const int lib = a.lib_ids ? a.lib_ids[slot] : slot;
+  const int64_t tbl = static_cast<int64_t>(slot) * a.tbl_stride;
+  lookup_body<K, kTMax>(a, a.E, lib, a.idx + tbl, a.w + tbl, a.tgt_ids,
+                        static_cast<int>(blockIdx.x) * T, T, a.ntgt, ys);
+}
+
+template <int K>
+__device__ __forceinline__ void lookup_item(const LookupArgs &a, const LookupItem &w, float *ys) {
+  const int64_t o = a.tbl_off[static_cast<int64_t>(w.lib) * (EDM_E_MAX + 1) + w.E];
+  lookup_body<K, kItemTMax>(a, w.E, w.lib, a.tbl_idx + o, a.tbl_w + o,
+                            a.bucket_ids + a.bucket_at[w.E], w.first, w.T, w.first + w.count, ys);
+}
+
+// Item kernel for one E (K = E + 1): persistent (counter != nullptr: loop
+// pulling items) or one workgroup per item.  Item fields are made
+// wave-uniform.
+template <int K>
+__global__ __launch_bounds__(kLookupThreads) void k_lookup_items(LookupArgs a,
+                                                                const LookupItem *__restrict__ items,
+                                                                int n_items, int *counter) {
+  extern __shared__ float ys[];
+  __shared__ int item_s;
+  // One call site for the body (a second one would make the inliner emit a
+  // real call with a scratch frame).  Without a counter each workgroup runs
+  // the item of its own index once.
+  for (int trip = 0;; ++trip) {
+    int it;
+    if (counter == nullptr) {
+      if (trip > 0) break;
+      it = static_cast<int>(blockIdx.x);
+    } else {
+      __syncthreads();
+      if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
+      __syncthreads();
+      it = __builtin_amdgcn_readfirstlane(item_s);
+      if (it >= n_items) break;
+    }
+    LookupItem w;
+    w.lib = __builtin_amdgcn_readfirstlane(items[it].lib);
+    w.E = static_cast<int16_t>(K - 1);
+    w.T = static_cast<int16_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(items[it].T)));
+    w.first = __builtin_amdgcn_readfirstlane(items[it].first);
+    w.count = __builtin_amdgcn_readfirstlane(items[it].count);
+    lookup_item<K>(a, w, ys);
   }
 }
 
@@ -165,6 +218,37 @@ hipError_t launch_lookup(const LookupArgs &a, int nslots, int64_t m_max, hipStre
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_lookup_items(const LookupArgs &a, int E, const LookupItem *items, int n_items,
+                               int *counter, int64_t lds_floats, int wg_per_cu, int n_cu,
+                               hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  using Fn = void (*)(LookupArgs, const LookupItem *, int, int *);
+#define EDM_FN(E) &k_lookup_items<E + 1>
+  static const Fn fns[EDM_E_MAX] = {EDM_FN(1),  EDM_FN(2),  EDM_FN(3),  EDM_FN(4),  EDM_FN(5),
+                                    EDM_FN(6),  EDM_FN(7),  EDM_FN(8),  EDM_FN(9),  EDM_FN(10),
+                                    EDM_FN(11), EDM_FN(12), EDM_FN(13), EDM_FN(14), EDM_FN(15),
+                                    EDM_FN(16), EDM_FN(17), EDM_FN(18), EDM_FN(19), EDM_FN(20)};
+#undef EDM_FN
+  if (E < 1 || E > EDM_E_MAX) return hipErrorInvalidValue;
+  const size_t shm = static_cast<size_t>(lds_floats) * sizeof(float);
+  const void *fn = reinterpret_cast<const void *>(fns[E - 1]);
+  if (shm > 65536) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(shm));
+    if (e != hipSuccess) return e;
+  }
+  if (wg_per_cu <= 0) {
+    hipLaunchKernelGGL(fns[E - 1], dim3(static_cast<unsigned>(n_items)), dim3(kLookupThreads), shm,
+                       st, a, items, n_items, static_cast<int *>(nullptr));
+  } else {
+    int grid = wg_per_cu * n_cu;
+    if (grid > n_items) grid = n_items;
+    hipLaunchKernelGGL(fns[E - 1], dim3(static_cast<unsigned>(grid)), dim3(kLookupThreads), shm, st,
+                       a, items, n_items, counter);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace edm

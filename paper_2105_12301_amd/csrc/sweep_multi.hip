@@ -71,14 +71,16 @@ __device__ __forceinline__ void slice_offer(float (&qk)[TOT], int (&qi)[TOT], fl
     slice_insert<OFF, K, TOT>(qk, qi, want ? key : __builtin_inff(), q);
 }
 
+// One workgroup's share of a batched scan: query block `bx` of row `row`,
+// every E in [ELO, EHI].  Called by the grid kernel and by the persistent
+// kernel; every early return is uniform across the workgroup.
 template <int ELO, int EHI>
-__global__ __launch_bounds__(kKnnThreads) void k_sweep_multi(KnnArgs a, int slot0) {
+__device__ __forceinline__ void group_scan(const KnnArgs &a, const int row, const int bx,
+                                           float *__restrict__ xs) {
   constexpr int NG = EHI - ELO + 1;
   constexpr int TOT = list_off<ELO>(EHI + 1);
-  extern __shared__ float xs[];
   __shared__ Mom wmom[kKnnThreads / kWave][NG];
-
-  const int row = slot0 + static_cast<int>(blockIdx.y);
+  const uint32_t need = a.need_dev ? a.need_dev[row] : a.need;
   const float *__restrict__ x = a.X + static_cast<int64_t>(row) * a.ldx;
   const int L = static_cast<int>(a.L_dev ? a.L_dev[row] : a.L_uni);
   const int Tp = a.Tp;
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(kKnnThreads) void k_sweep_multi(KnnArgs a, int slot
   const int m_lo = L - (ELO - 1) - Tp;
   const int m_hi = L - (EHI - 1) - Tp;
   if (m_lo - 1 < ELO + 1) return;  // no E of the group is feasible
-  const int blk0 = static_cast<int>(blockIdx.x) * kKnnThreads;
+  const int blk0 = bx * kKnnThreads;
   if (blk0 >= m_lo) return;
 
   bool bad = false;
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(kKnnThreads) void k_sweep_multi(KnnArgs a, int slot
     constexpr int E = decltype(EC)::value;
     constexpr int OFF = list_off<ELO>(E);
     // table mode: lists of E that are not needed stay idle (kth = -1)
-    const bool act = p < L - (E - 1) - Tp && (a.mom != nullptr || ((a.need >> (E - 1)) & 1u));
+    const bool act = p < L - (E - 1) - Tp && (a.mom != nullptr || ((need >> (E - 1)) & 1u));
 #pragma unroll
     for (int i = 0; i < E + 1; ++i) {
       qk[OFF + i] = act ? __builtin_inff() : -1.0f;
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(kKnnThreads) void k_sweep_multi(KnnArgs a, int slot
     constexpr int OFF = list_off<ELO>(E);
     const int mE = L - (E - 1) - Tp;
     Mom mine = mom_zero();
-    const bool want_table = a.mom == nullptr && ((a.need >> (E - 1)) & 1u);
+    const bool want_table = a.mom == nullptr && ((need >> (E - 1)) & 1u);
     if (p < mE && mE - 1 >= K && (a.mom != nullptr || want_table)) {
       double D[K];
       double dmin = __builtin_inf();
@@ -234,11 +236,23 @@ __global__ __launch_bounds__(kKnnThreads) void k_sweep_multi(KnnArgs a, int slot
       }
       const double inv = 1.0 / wsum;
       if (want_table) {
-        const int64_t base = static_cast<int64_t>(row) * a.strideE[E] + static_cast<int64_t>(p) * K;
+        int32_t *ti;
+        float *tw;
+        int64_t base;
+        if (a.tbl_off) {
+          const int64_t o = a.tbl_off[static_cast<int64_t>(row) * (EDM_E_MAX + 1) + E];
+          ti = a.tbl_idx + o;
+          tw = a.tbl_w + o;
+          base = static_cast<int64_t>(p) * K;
+        } else {
+          ti = a.idxE[E];
+          tw = a.wE[E];
+          base = static_cast<int64_t>(row) * a.strideE[E] + static_cast<int64_t>(p) * K;
+        }
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-          a.idxE[E][base + i] = qi[OFF + i];
-          a.wE[E][base + i] = static_cast<float>(D[i] * inv);
+          ti[base + i] = qi[OFF + i];
+          tw[base + i] = static_cast<float>(D[i] * inv);
         }
       } else {
         const int o_off = (E - 1) + Tp;
@@ -264,8 +278,42 @@ __global__ __launch_bounds__(kKnnThreads) void k_sweep_multi(KnnArgs a, int slot
       Mom t = wmom[0][threadIdx.x];
 #pragma unroll
       for (int w = 1; w < kKnnThreads / kWave; ++w) t = mom_merge(t, wmom[w][threadIdx.x]);
-      a.mom[(static_cast<int64_t>(row) * a.E_max + (E - 1)) * a.mom_blocks + blockIdx.x] = t;
+      a.mom[(static_cast<int64_t>(row) * a.E_max + (E - 1)) * a.mom_blocks + bx] = t;
     }
+  }
+}
+
+template <int ELO, int EHI>
+__global__ __launch_bounds__(kKnnThreads) void k_sweep_multi(KnnArgs a, int slot0) {
+  extern __shared__ float xs[];
+  group_scan<ELO, EHI>(a, slot0 + static_cast<int>(blockIdx.y), static_cast<int>(blockIdx.x), xs);
+}
+
+// Persistent form: each workgroup pulls (row, block) items of one E group,
+// ordered by the host longest first, from a device counter until the list is
+// exhausted (every workgroup reaches the exit).  The item index travels
+// through LDS and is made wave-uniform.
+template <int ELO, int EHI>
+__global__ __launch_bounds__(kKnnThreads) void k_tables_persistent(KnnArgs a,
+                                                                   const TableItem *__restrict__ items,
+                                                                   int n_items, int *counter) {
+  extern __shared__ float xs[];
+  __shared__ int item_s;
+  for (int trip = 0;; ++trip) {  // one call site for the body (see lookup.hip)
+    int it;
+    if (counter == nullptr) {  // one item per workgroup
+      if (trip > 0) break;
+      it = static_cast<int>(blockIdx.x);
+    } else {
+      __syncthreads();  // the previous item is done with xs and item_s
+      if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
+      __syncthreads();
+      it = __builtin_amdgcn_readfirstlane(item_s);
+      if (it >= n_items) break;
+    }
+    const int row = __builtin_amdgcn_readfirstlane(items[it].row);
+    const int blk = __builtin_amdgcn_readfirstlane(static_cast<int>(items[it].blk));
+    group_scan<ELO, EHI>(a, row, blk, xs);
   }
 }
 
@@ -324,6 +372,34 @@ hipError_t launch_sweep_multi(const KnnArgs &a, int nslots, int64_t L_max, hipSt
     }
   }
   return hipSuccess;
+}
+
+hipError_t launch_tables_persistent(const KnnArgs &a, int group, const TableItem *items,
+                                    int n_items, int *counter, int64_t L_max, int wg_per_cu,
+                                    int n_cu, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  using Fn = void (*)(KnnArgs, const TableItem *, int, int *);
+  static const Fn fns[5] = {&k_tables_persistent<1, 8>, &k_tables_persistent<9, 12>,
+                            &k_tables_persistent<13, 15>, &k_tables_persistent<16, 18>,
+                            &k_tables_persistent<19, 20>};
+  if (group < 0 || group > 4) return hipErrorInvalidValue;
+  const size_t shm = static_cast<size_t>(L_max) * sizeof(float);
+  const void *fn = reinterpret_cast<const void *>(fns[group]);
+  if (shm > 65536) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(shm));
+    if (e != hipSuccess) return e;
+  }
+  if (wg_per_cu <= 0) {  // one workgroup per item
+    hipLaunchKernelGGL(fns[group], dim3(static_cast<unsigned>(n_items)), dim3(kKnnThreads), shm, st,
+                       a, items, n_items, static_cast<int *>(nullptr));
+    return hipGetLastError();
+  }
+  int grid = wg_per_cu * n_cu;
+  if (grid > n_items) grid = n_items;
+  hipLaunchKernelGGL(fns[group], dim3(static_cast<unsigned>(grid)), dim3(kKnnThreads), shm, st, a,
+                     items, n_items, counter);
+  return hipGetLastError();
 }
 
 }  // namespace edm

@@ -43,7 +43,17 @@ EXPORTS = (
     "edm_simplex_sweep", "edm_ccm",
     "edm_net_param_count", "edm_net_forward", "edm_net_loss_grad", "edm_net_adam",
     "edm_select_E",
+    "edm_tune_default", "edm_ccm_plan_create", "edm_ccm_plan_run", "edm_ccm_plan_destroy",
 )
+
+
+class Tune(ctypes.Structure):
+    """Launch shapes of a batched CCM plan (edm_tune)."""
+    _fields_ = [("tables_wg_per_cu", ctypes.c_int32), ("lookup_wg_per_cu", ctypes.c_int32),
+                ("lookup_targets", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class EdmError(RuntimeError):
@@ -89,8 +99,16 @@ def load_library(path: str = LIB_PATH):
                                      ctypes.c_float, ctypes.c_float, ctypes.c_float]
         lib.edm_select_E.argtypes = [_p, _p, _p, _i64, _i64, _i32, _i32, _i32, _p, _i32,
                                      ctypes.c_float, _p, _p, ctypes.POINTER(_i64)]
+        lib.edm_tune_default.argtypes = [ctypes.POINTER(Tune)]
+        lib.edm_tune_default.restype = None
+        lib.edm_ccm_plan_create.argtypes = [_p, _p, _i64, _i64, _p, _i64, _i64, _p, _i32,
+                                            ctypes.POINTER(Tune), ctypes.POINTER(_p)]
+        lib.edm_ccm_plan_run.argtypes = [_p, _p, _p, _p, _p]
+        lib.edm_ccm_plan_destroy.argtypes = [_p, _p]
+        lib.edm_ccm_plan_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("edm_last_error", "edm_ctx_destroy", "edm_net_param_count"):
+            if name not in ("edm_last_error", "edm_ctx_destroy", "edm_net_param_count",
+                            "edm_tune_default", "edm_ccm_plan_destroy"):
                 getattr(lib, name).restype = ctypes.c_int
         _lib = lib
         return lib
@@ -328,3 +346,53 @@ def edm_select_E(X, logits, lengths=None, E_max: int = E_MAX, tau: int = 1, Tp: 
         _dev_ptr(rho, torch.float32, "rho"), _dev_ptr(E_opt, torch.int32, "E_opt"),
         ctypes.byref(nfb)), ctx.handle)
     return rho, E_opt, int(nfb.value)
+
+
+# ---------------------------------------------------------------- plan ------
+def default_tune() -> Tune:
+    t = Tune()
+    load_library().edm_tune_default(ctypes.byref(t))
+    return t
+
+
+class CcmPlan:
+    """Batched all-to-all CCM over libraries of uneven length (edm_ccm_plan_*).
+
+    Built once from host lengths and target E values; ``run`` replays a
+    captured HIP graph when the context's stream is not the legacy default
+    stream."""
+
+    def __init__(self, Lx, Ly, E_tgt, ldx: int, ldy: int, Tp: int = 0, tune: Tune | None = None,
+                 ctx: Context | None = None):
+        self.ctx = ctx or default_context()
+        self.Lx = _host_i64(Lx, len(Lx), "Lx")
+        self.Ly = _host_i64(Ly, len(Ly), "Ly")
+        E = np.ascontiguousarray(np.asarray(E_tgt.cpu() if isinstance(E_tgt, torch.Tensor) else E_tgt,
+                                            dtype=np.int32))
+        self.Nl, self.Nt = len(self.Lx), len(self.Ly)
+        h = ctypes.c_void_p()
+        _check(load_library().edm_ccm_plan_create(
+            self.ctx.handle, self.Lx.ctypes.data_as(_p), self.Nl, int(ldx), self.Ly.ctypes.data_as(_p),
+            self.Nt, int(ldy), E.ctypes.data_as(_p), int(Tp), ctypes.byref(tune) if tune else None,
+            ctypes.byref(h)), self.ctx.handle)
+        self._h = h
+
+    def run(self, X, Y=None, rho=None):
+        Y = X if Y is None else Y
+        if rho is None:
+            rho = torch.empty((self.Nl, self.Nt), dtype=torch.float32, device=X.device)
+        _check(load_library().edm_ccm_plan_run(self.ctx.handle, self._h, _dev_ptr(X, torch.float32, "X"),
+                                               _dev_ptr(Y, torch.float32, "Y"),
+                                               _dev_ptr(rho, torch.float32, "rho")), self.ctx.handle)
+        return rho
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().edm_ccm_plan_destroy(self.ctx.handle, self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,84 @@
+"""Batched CCM plan (persistent launches, graph replay) against edm_ccm and the
+oracle, on libraries of uneven length with per-target E."""
+import numpy as np
+import pytest
+
+from oracle import edm_oracle as O
+from paper_2105_12301_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def edm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_12301_amd import edm as _edm
+
+    _edm.load_library()
+    return _edm
+
+
+@pytest.fixture(scope="module")
+def side():
+    s = torch.cuda.Stream()  # default priority; graphs cannot capture the legacy stream
+    return s
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+TUNES = [dict(tables_wg_per_cu=0, lookup_wg_per_cu=0, lookup_targets=4),
+         dict(tables_wg_per_cu=1, lookup_wg_per_cu=4, lookup_targets=2),
+         dict(tables_wg_per_cu=2, lookup_wg_per_cu=8, lookup_targets=1)]
+
+
+@pytest.mark.parametrize("tune", TUNES, ids=["grid", "persistent-1", "persistent-2"])
+@pytest.mark.parametrize("limit", [None, 4 << 20])
+def test_plan_equals_ccm_bitwise(edm, side, tune, limit, monkeypatch):
+    if limit:
+        monkeypatch.setenv("EDM_WORKSPACE_LIMIT", str(limit))
+    from paper_2105_12301_amd.autotune import make_tune
+    X, lens, E = synth.spike_trains(seed=21, N=48, L_min=150, L_max=1400)
+    E[5] = 0
+    with torch.cuda.stream(side):
+        ctx = edm.Context(device=0, stream=side)
+        Xd = dev(X)
+        ref = edm.edm_ccm(Xd, dev(E), Lx=lens, Ly=lens, ctx=ctx)
+        plan = edm.CcmPlan(lens, lens, E, X.shape[1], X.shape[1], tune=make_tune(tune), ctx=ctx)
+        r1 = plan.run(Xd).clone()   # captures the graph
+        r2 = plan.run(Xd).clone()   # replays it
+        ctx.sync()
+        assert torch.equal(ref.view(torch.int32), r1.view(torch.int32))
+        assert torch.equal(r1.view(torch.int32), r2.view(torch.int32))
+        plan.close()
+        ctx.close()
+
+
+def test_plan_matches_oracle_and_default_stream(edm):
+    X, lens, E = synth.spike_trains(seed=22, N=20, L_min=200, L_max=900)
+    ctx = edm.Context(device=0)   # legacy stream: enqueued without a graph
+    plan = edm.CcmPlan(lens, lens, E, X.shape[1], X.shape[1], ctx=ctx)
+    r = plan.run(dev(X))
+    ctx.sync()
+    ro = O.ccm(X, lens, X, lens, E, lib_rows=[0, 7, 19])
+    g = r.cpu().numpy()[[0, 7, 19]]
+    assert np.array_equal(np.isnan(g), np.isnan(ro))
+    assert np.nanmax(np.abs(g - ro)) <= 1e-5
+    plan.close()
+
+
+def test_autotune_picks_a_candidate(edm, side, tmp_path, monkeypatch):
+    monkeypatch.setenv("EDM_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    from paper_2105_12301_amd import autotune
+    X, lens, E = synth.spike_trains(seed=23, N=32, L_min=300, L_max=1200)
+    with torch.cuda.stream(side):
+        ctx = edm.Context(device=0, stream=side)
+        Xd = dev(X)
+        t, times = autotune.autotune(Xd, lens, Xd, lens, E, ctx=ctx, sample=8, reps=1)
+        assert len(times) == len(autotune.CANDIDATES)
+        t2, _ = autotune.autotune(Xd, lens, Xd, lens, E, ctx=ctx, sample=8, reps=1)   # cached
+        assert t.as_dict() == t2.as_dict()
+        ctx.close()
