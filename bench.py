@@ -147,13 +147,15 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--form", choices=("plain", "chosen", "both"), default="both",
-                    help="both: time the plain form, then the chosen form; value is the chosen form's")
+    ap.add_argument("--form", choices=("plain", "batched", "chosen", "both", "all"), default="all",
+                    help="all: time plain, batched and chosen forms; both: plain and chosen; "
+                         "value is the last form's (the chosen form unless one form is asked for)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cores", type=int, default=0, help="CPU baseline workers (0: min(16, cpus))")
-    ap.add_argument("--workload", choices=("network", "uneven", "learned"), default="network",
-                    help="network: the headline step; uneven / learned: the batching and "
-                         "learned-E variants on their own workloads")
+    ap.add_argument("--workload", choices=("network", "uneven", "learned", "precision"),
+                    default="network",
+                    help="network: the headline step; uneven / learned / precision: the batching, "
+                         "learned-E and matrix-core filter variants on their own workloads")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -172,6 +174,9 @@ def main(argv=None):
     if args.workload == "learned":
         print(json.dumps(bench_learned(args, torch, edm, synth)))
         return 0
+    if args.workload == "precision":
+        print(json.dumps(bench_precision(args, torch, edm, synth)))
+        return 0
 
     w = WORKLOAD
     X, _, _ = synth.logistic_network(seed=w["seed"], N=w["N"], L=w["L"])
@@ -183,17 +188,22 @@ def main(argv=None):
     rho = torch.empty((N, N), dtype=torch.float32, device=dev)
     pairs = N * N
 
-    forms = {"plain": [edm.EDM_FORM_PLAIN], "chosen": [edm.EDM_FORM_CHOSEN],
-             "both": [edm.EDM_FORM_PLAIN, edm.EDM_FORM_CHOSEN]}[args.form]
+    names = {edm.EDM_FORM_PLAIN: "plain", edm.EDM_FORM_BATCHED: "batched", edm.EDM_FORM_CHOSEN: "chosen"}
+    forms = {"plain": [edm.EDM_FORM_PLAIN], "batched": [edm.EDM_FORM_BATCHED],
+             "chosen": [edm.EDM_FORM_CHOSEN],
+             "both": [edm.EDM_FORM_PLAIN, edm.EDM_FORM_CHOSEN],
+             "all": [edm.EDM_FORM_PLAIN, edm.EDM_FORM_BATCHED, edm.EDM_FORM_CHOSEN]}[args.form]
     res = {}
     for f in forms:
         res[f] = run_form(edm, ctx, Xd, rho, w, args.steps, args.warmup, f)
     main_form = forms[-1]
     r = res[main_form]
-    form_name = "chosen" if main_form == edm.EDM_FORM_CHOSEN else "plain"
-    if main_form == edm.EDM_FORM_CHOSEN:
+    form_name = names[main_form]
+    if main_form != edm.EDM_FORM_PLAIN:
         ops = batched_sweep_ops(N, L, w["E_max"], w["tau"], w["Tp_sweep"])
-        kernel = "k_sweep_multi (batched E sweep: fused embed+distance+top-k+weights+self-lookup), all groups of one sweep"
+        kernel = ("one batched E sweep (k_sweep_multi groups"
+                  + (" 1-8 + matrix-core filtered k_gram groups 9-20" if main_form == edm.EDM_FORM_CHOSEN else "")
+                  + "): fused embed+distance+top-k+weights+self-lookup; ops counted as the exact batched scan's")
     else:
         ops = sweep_ops(N, L, w["E_max"], w["tau"], w["Tp_sweep"])
         kernel = "k_knn (fused embed+distance+top-k+weights+self-lookup), all E of one sweep"
@@ -233,20 +243,24 @@ def main(argv=None):
             "ops_per_sweep": ops,
         },
     }
-    if "plain" in [("plain" if f == edm.EDM_FORM_PLAIN else "chosen") for f in forms] and len(forms) > 1:
-        p = res[edm.EDM_FORM_PLAIN]
-        ops_p = sweep_ops(N, L, w["E_max"], w["tau"], w["Tp_sweep"])
-        out["plain"] = {
-            "value": pairs / (p["ms_per_step"] / 1e3),
-            "ms_per_step": p["ms_per_step"],
-            "breakdown_ms": {"sweep": p["sweep_ms"], "ccm": p["ccm_ms"]},
-            "roofline_frac": ops_p / (p["sweep_ms"] / 1e3) / ALU_PEAK_OPS,
-        }
-        out["speedup_vs_plain"] = p["ms_per_step"] / r["ms_per_step"]
+    for f in forms[:-1]:
+        p = res[f]
+        ops_f = sweep_ops(N, L, w["E_max"], w["tau"], w["Tp_sweep"]) if f == edm.EDM_FORM_PLAIN else \
+            batched_sweep_ops(N, L, w["E_max"], w["tau"], w["Tp_sweep"])
         same = (np.array_equal(p["rs"].view(np.int32), r["rs"].view(np.int32))
                 and np.array_equal(p["Es"], r["Es"])
                 and np.array_equal(p["rho"].view(np.int32), r["rho"].view(np.int32)))
-        out["chosen_bit_identical_to_plain"] = bool(same)
+        out[names[f]] = {
+            "value": pairs / (p["ms_per_step"] / 1e3),
+            "ms_per_step": p["ms_per_step"],
+            "breakdown_ms": {"sweep": p["sweep_ms"], "ccm": p["ccm_ms"]},
+            "roofline_frac": ops_f / (p["sweep_ms"] / 1e3) / ALU_PEAK_OPS,
+            "speedup_of_" + form_name: p["ms_per_step"] / r["ms_per_step"],
+            form_name + "_bit_identical": bool(same),
+        }
+    if edm.EDM_FORM_PLAIN in res and main_form != edm.EDM_FORM_PLAIN:
+        out["speedup_vs_plain"] = res[edm.EDM_FORM_PLAIN]["ms_per_step"] / r["ms_per_step"]
+        out[form_name + "_bit_identical_to_plain"] = out["plain"][form_name + "_bit_identical"]
 
     if not args.no_cpu_baseline:
         cores = args.cores or min(16, os.cpu_count() or 1)
@@ -429,6 +443,102 @@ def bench_learned(args, torch, edm, synth):
                       "mean_rho_loss": float(np.mean(best - got)),
                       "max_rho_loss": float(np.max(best - got))},
     }
+    ctx.close()
+    return out
+
+
+def bench_precision(args, torch, edm, synth):
+    """Calcium-like traces: 10000 series, L = 2000, 20% of them modulated by 20
+    latent logistic drivers.  One step = simplex E sweep (1..20, Tp = 1) and
+    the full 10000 x 10000 CCM (Tp = 0).  Plain, batched and chosen forms
+    (the chosen form adds the BF16 matrix-core filter with exact re-rank);
+    value = the chosen form's pairs/s.  rho is checked against the oracle on a
+    16 x 16 subset with E* from the plain sweep."""
+    X, group = synth.calcium_like(seed=4)
+    N, L = X.shape
+    torch.cuda.set_device(0)
+    Xd = torch.from_numpy(X).cuda()
+    ctx = edm.Context(device=0)
+    rho = torch.empty((N, N), dtype=torch.float32, device="cuda")
+    stream = ctx.stream
+    pairs = N * N
+
+    def run(form):
+        ctx.set_form(form)
+
+        def step():
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record(stream)
+            rs, Es = edm.edm_simplex_sweep(Xd, E_max=20, Tp=1, ctx=ctx)
+            ev[1].record(stream)
+            edm.edm_ccm(Xd, Es, Tp=0, rho=rho, ctx=ctx)
+            ev[2].record(stream)
+            return ev, rs, Es
+
+        for _ in range(args.warmup):
+            step()
+        ctx.sync()
+        evs = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ev, rs, Es = step()
+            evs.append(ev)
+        ctx.sync()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / args.steps
+        return dict(ms=wall, sweep_ms=float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
+                    ccm_ms=float(np.mean([e[1].elapsed_time(e[2]) for e in evs])),
+                    rs=rs.cpu().numpy(), Es=Es.cpu().numpy(), rho=rho.cpu().numpy())
+
+    names = {edm.EDM_FORM_PLAIN: "plain", edm.EDM_FORM_BATCHED: "batched", edm.EDM_FORM_CHOSEN: "chosen"}
+    res = {f: run(f) for f in (edm.EDM_FORM_PLAIN, edm.EDM_FORM_BATCHED, edm.EDM_FORM_CHOSEN)}
+    r = res[edm.EDM_FORM_CHOSEN]
+    out = {
+        "metric": "CCM pairs/sec at rho err <=1e-5 vs FP64 oracle; chosen (BF16 filter) vs plain form, 1 GPU",
+        "value": pairs / (r["ms"] / 1e3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "calcium-like 10000 series x L=2000 (20% driven by 20 latent logistic maps); "
+                               "E sweep 1..20 (Tp=1) then full 10000x10000 CCM (Tp=0)",
+                   "form": "chosen"},
+        "breakdown_ms": {"sweep": r["sweep_ms"], "ccm": r["ccm_ms"]},
+        "E_star_hist": np.bincount(r["Es"], minlength=21)[1:].tolist(),
+    }
+    for f in (edm.EDM_FORM_PLAIN, edm.EDM_FORM_BATCHED):
+        p = res[f]
+        same = (np.array_equal(p["rs"].view(np.int32), r["rs"].view(np.int32))
+                and np.array_equal(p["Es"], r["Es"])
+                and np.array_equal(p["rho"].view(np.int32), r["rho"].view(np.int32)))
+        out[names[f]] = {"value": pairs / (p["ms"] / 1e3), "ms_per_step": p["ms"],
+                         "breakdown_ms": {"sweep": p["sweep_ms"], "ccm": p["ccm_ms"]},
+                         "speedup_of_chosen": p["ms"] / r["ms"], "chosen_bit_identical": bool(same)}
+    out["speedup_vs_plain"] = out["plain"]["speedup_of_chosen"]
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(4)
+        driven = [np.nonzero(group == g)[0][:4] for g in (0, 1)]
+        others = rng.choice(np.nonzero(group < 0)[0], size=8, replace=False)
+        libs = np.sort(np.r_[driven[0], driven[1], others])
+        tgts = np.sort(np.r_[driven[0][::-1], driven[1][::-1],
+                             rng.choice(np.setdiff1d(np.arange(N), libs), size=8, replace=False)])
+        E_plain = res[edm.EDM_FORM_PLAIN]["Es"]
+        tasks = [(X[i], L, X[tgts], np.full(len(tgts), L), E_plain[tgts], np.arange(len(tgts)), 0)
+                 for i in libs]
+        import multiprocessing as mp
+        cores = min(args.cores or min(16, os.cpu_count() or 1), len(tasks))
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(cores) as pool:
+            rows = pool.map(_oracle_pairs_task, tasks)
+        wall = time.perf_counter() - t0
+        g = r["rho"][np.ix_(libs, tgts)]
+        o = np.array(rows)
+        err = float(np.nanmax(np.abs(g - o)))
+        out["cpu_baseline"] = {"value": len(libs) * len(tgts) / wall, "unit": "pairs/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": "256 pairs: 16 libraries (8 sharing two latent drivers) x 16 targets, "
+                                         "E* from the plain sweep"}
+        out["parity"] = {"max_abs_rho_err": err, "nan_match": bool(np.array_equal(np.isnan(g), np.isnan(o))),
+                         "E_star_equal_plain": bool(np.array_equal(E_plain, r["Es"])),
+                         "ok": bool(err <= 1e-5)}
     ctx.close()
     return out
 

@@ -54,12 +54,17 @@ extern "C" {
 typedef struct edm_ctx edm_ctx;
 
 /* Form of the computation (results are identical; only the schedule differs).
- * EDM_FORM_PLAIN : one candidate scan per (library, E), float32 VALU keys.
- * EDM_FORM_CHOSEN: edm_simplex_sweep with tau = 1 runs one candidate scan per
- *                  group of E values, extending one running key (the key for
- *                  E is the key for E-1 plus one rounded term), so tables,
- *                  rho and E_opt are bit-identical to the plain form. */
-typedef enum { EDM_FORM_PLAIN = 0, EDM_FORM_CHOSEN = 1 } edm_form;
+ * EDM_FORM_PLAIN  : one candidate scan per (library, E), float32 VALU keys.
+ * EDM_FORM_BATCHED: with tau = 1, edm_simplex_sweep and edm_ccm run one
+ *                   candidate scan per group of E values, extending one
+ *                   running key (the key for E is the key for E-1 plus one
+ *                   rounded term).
+ * EDM_FORM_CHOSEN : EDM_FORM_BATCHED, and for E >= 9 (series up to 16384
+ *                   samples) a BF16 matrix-core estimate of every key filters
+ *                   the candidates; the ones that may enter a top-k list are
+ *                   re-ranked with the exact float32 key.
+ * Tables, rho and E_opt are bit-identical across the three forms. */
+typedef enum { EDM_FORM_PLAIN = 0, EDM_FORM_CHOSEN = 1, EDM_FORM_BATCHED = 2 } edm_form;
 
 enum {
   EDM_OK = 0,
@@ -114,7 +119,9 @@ int edm_embed(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau,
  * w    : float32 [nq][k] simplex weights exp(-d_i/min d) / sum, Section 2.1
  *        step 3; when min d = 0 the weights are 1 at zero distance and 0
  *        elsewhere before normalising                               (or NULL)
- * nq = L - (E-1)*tau - Tp. */
+ * nq = L - (E-1)*tau - Tp.
+ * In EDM_FORM_CHOSEN with tau = 1, k = E+1, E >= 9, L <= 16384 and dist ==
+ * NULL, the table comes from the matrix-core filtered scan (same result). */
 int edm_knn(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau,
             int32_t Tp, int32_t k, int32_t *idx, float *dist, float *w);
 
@@ -222,6 +229,13 @@ int64_t edm_net_param_count(int32_t C);
 /* Forward pass: logits[B][20] (float32, device); class c is E = c + 1. */
 int edm_net_forward(edm_ctx *ctx, const float *params, int32_t C, const float *X, int64_t B,
                     int64_t L, int64_t ldx, float *logits);
+
+/* Inference form of edm_net_forward: the two C -> C convolutions run on the
+ * BF16 matrix cores (inputs and weights rounded to BF16, FP32 accumulation);
+ * layer 1, pooling and the linear layer stay float32.  C must be 32 or 64.
+ * Training uses edm_net_loss_grad (float32 throughout). */
+int edm_net_forward_bf16(edm_ctx *ctx, const float *params, int32_t C, const float *X, int64_t B,
+                         int64_t L, int64_t ldx, float *logits);
 
 /* Mean softmax cross-entropy of the batch against labels[B] (int32 E in
  * 1..20, device) and its gradient with respect to the parameters.

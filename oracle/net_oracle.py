@@ -77,6 +77,30 @@ def forward(theta, X, C: int, kw: int = KW):
     return logits, (x, a1, a2, a3, g)
 
 
+def bf16_round(a):
+    """Round to the nearest BF16 value (8 significant bits, ties to even),
+    through float32 first (the GPU holds these values in float32); returned
+    as float64.  BF16 is the upper half of an IEEE float32."""
+    f = np.asarray(a, np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def forward_bf16(theta, X, C: int, kw: int = KW):
+    """Inference forward pass of the BF16 form: layer 1 as in ``forward``;
+    the inputs and weights of the two C -> C convolutions rounded to BF16
+    (their products are exact), sums, bias, ReLU, pooling and the linear
+    layer in float64.  Returns logits [B][20]."""
+    p = unpack(theta, C, kw)
+    x = np.asarray(X, np.float64)[:, None, :]
+    a1 = np.maximum(conv_same(x, p["w1"], p["b1"]), 0.0)
+    a2 = np.maximum(conv_same(bf16_round(a1), bf16_round(p["w2"]), p["b2"]), 0.0)
+    a3 = np.maximum(conv_same(bf16_round(a2), bf16_round(p["w3"]), p["b3"]), 0.0)
+    g = a3.mean(axis=2)
+    return g @ p["wo"].T + p["bo"]
+
+
 def softmax(logits):
     z = logits - logits.max(axis=1, keepdims=True)
     e = np.exp(z)

@@ -134,7 +134,7 @@ int edm_ctx_create(edm_ctx **out, void *hip_stream) {
 
 int edm_ctx_set_form(edm_ctx *ctx, int form) {
   EDM_RC(check_ctx(ctx));
-  if (form != EDM_FORM_PLAIN && form != EDM_FORM_CHOSEN)
+  if (form != EDM_FORM_PLAIN && form != EDM_FORM_CHOSEN && form != EDM_FORM_BATCHED)
     return set_err(ctx, EDM_E_ARG, "unknown form");
   ctx->form = form;
   return EDM_OK;
@@ -181,6 +181,36 @@ int edm_knn(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau, int
   const int rc = edm::check_knn(x, L, E, tau, Tp, k, idx, msg);
   if (rc != EDM_OK) return set_err(ctx, rc, msg);
   EDM_RC(check_ctx(ctx));
+  if (ctx->form == EDM_FORM_CHOSEN && tau == 1 && (k == 0 || k == E + 1) && dist == nullptr &&
+      E >= edm::kGramEMin && L <= edm::kGramLMax) {
+    // Chosen form: the table of one E through the matrix-core filter (the
+    // filtered group scan in table mode; the group's other lists stay idle).
+    const int64_t nq = L - (E - 1) - Tp;
+    const int64_t g_ld = edm::gram_ld(L);
+    Plan plan;
+    const size_t off_mu = plan.take(sizeof(float));
+    const size_t off_nrm = plan.take(sizeof(uint32_t) * static_cast<size_t>(edm::kGramNE) * g_ld);
+    const size_t off_w = plan.take(w ? 0 : sizeof(float) * static_cast<size_t>(nq) * (E + 1));
+    EDM_RC(ws_reserve(ctx, plan.bytes));
+    edm::KnnArgs a{};
+    a.X = x;
+    a.ldx = L;
+    a.L_uni = L;
+    a.tau = 1;
+    a.Tp = Tp;
+    a.E_max = EDM_E_MAX;
+    a.status = ctx->status;
+    a.need = 1u << (E - 1);
+    a.idxE[E] = idx;
+    a.wE[E] = w ? w : reinterpret_cast<float *>(ctx->ws + off_w);
+    a.strideE[E] = nq * (E + 1);
+    a.gram_mu = reinterpret_cast<float *>(ctx->ws + off_mu);
+    a.gram_nrm = reinterpret_cast<uint32_t *>(ctx->ws + off_nrm);
+    a.gram_ld = g_ld;
+    EDM_HIP(ctx, edm::launch_gram_prep(a, 1, L, ctx->stream));
+    EDM_HIP(ctx, edm::launch_sweep_multi(a, 1, L, ctx->stream));
+    return EDM_OK;
+  }
   edm::KnnArgs a{};
   a.X = x;
   a.ldx = L;
@@ -244,27 +274,54 @@ int edm_simplex_sweep(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N,
   if (N > INT32_MAX) return set_err(ctx, EDM_E_ARG, "too many series");
   const int64_t L_max = *std::max_element(L, L + N);
   const int32_t mom_blocks = static_cast<int32_t>((L_max + edm::kKnnThreads - 1) / edm::kKnnThreads);
+  const bool batched = (ctx->form == EDM_FORM_CHOSEN || ctx->form == EDM_FORM_BATCHED) && tau == 1;
+  const bool gram = batched && ctx->form == EDM_FORM_CHOSEN && E_max >= edm::kGramEMin &&
+                    L_max <= edm::kGramLMax;
+  const int64_t g_ld = edm::gram_ld(L_max);
+  const size_t g_row = sizeof(uint32_t) * static_cast<size_t>(edm::kGramNE) * g_ld + sizeof(float);
   Plan plan;
   const size_t off_L = plan.take(sizeof(int64_t) * N);
   const size_t off_mom = plan.take(edm::kMomBytes * static_cast<size_t>(N) * E_max * mom_blocks);
+  // Filter norms for a batch of rows (at most 1 GiB, at least one row).
+  int64_t g_batch = 0;
+  size_t off_gmu = 0, off_gnrm = 0;
+  if (gram) {
+    g_batch = std::max<int64_t>(1, std::min<int64_t>(N, static_cast<int64_t>((size_t(1) << 30) / g_row)));
+    off_gmu = plan.take(sizeof(float) * g_batch);
+    off_gnrm = plan.take(sizeof(uint32_t) * static_cast<size_t>(edm::kGramNE) * g_ld * g_batch);
+  }
   if (plan.bytes > workspace_limit()) return set_err(ctx, EDM_E_NOMEM, "sweep workspace exceeds EDM_WORKSPACE_LIMIT");
   EDM_RC(ws_reserve(ctx, plan.bytes));
   int64_t *L_dev = reinterpret_cast<int64_t *>(ctx->ws + off_L);
   edm::Mom *mom = reinterpret_cast<edm::Mom *>(ctx->ws + off_mom);
   EDM_RC(upload(ctx, L, sizeof(int64_t) * N, L_dev));
-  if (ctx->form == EDM_FORM_CHOSEN && tau == 1) {
-    // Batched form: one candidate scan per group of E values.
-    edm::KnnArgs a{};
-    a.X = X;
-    a.ldx = ldx;
-    a.L_dev = L_dev;
-    a.Tp = Tp;
-    a.tau = 1;
-    a.mom = mom;
-    a.mom_blocks = mom_blocks;
-    a.E_max = E_max;
-    a.status = ctx->status;
-    EDM_HIP(ctx, edm::launch_sweep_multi(a, static_cast<int>(N), L_max, ctx->stream));
+  if (batched) {
+    // Batched form: one candidate scan per group of E values (through the
+    // matrix-core filter for E >= 9 in the chosen form).
+    const int64_t step = gram ? g_batch : N;
+    for (int64_t b0 = 0; b0 < N; b0 += step) {
+      const int64_t nb = std::min<int64_t>(step, N - b0);
+      edm::KnnArgs a{};
+      a.X = X + b0 * ldx;
+      a.ldx = ldx;
+      a.L_dev = L_dev + b0;
+      a.Tp = Tp;
+      a.tau = 1;
+      a.mom = reinterpret_cast<edm::Mom *>(reinterpret_cast<char *>(mom) +
+                                           edm::kMomBytes * static_cast<size_t>(b0 * E_max) * mom_blocks);
+      a.mom_blocks = mom_blocks;
+      a.E_max = E_max;
+      a.status = ctx->status;
+      int64_t L_b = L_max;
+      if (gram) {
+        L_b = *std::max_element(L + b0, L + b0 + nb);
+        a.gram_mu = reinterpret_cast<float *>(ctx->ws + off_gmu);
+        a.gram_nrm = reinterpret_cast<uint32_t *>(ctx->ws + off_gnrm);
+        a.gram_ld = g_ld;
+        EDM_HIP(ctx, edm::launch_gram_prep(a, static_cast<int>(nb), L_b, ctx->stream));
+      }
+      EDM_HIP(ctx, edm::launch_sweep_multi(a, static_cast<int>(nb), L_b, ctx->stream));
+    }
   } else {
   for (int E = 1; E <= E_max; ++E) {
     edm::KnnArgs a{};
@@ -320,7 +377,12 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
   const size_t off_tbl = plan.take(0);
   // Table bytes of one library: the largest E in use (plain form, one E at a
   // time) or every E in use together (chosen form, one scan per E group).
-  const bool batched = ctx->form == EDM_FORM_CHOSEN && tau == 1;
+  const bool batched = (ctx->form == EDM_FORM_CHOSEN || ctx->form == EDM_FORM_BATCHED) && tau == 1;
+  const bool gram = batched && ctx->form == EDM_FORM_CHOSEN && Lx_max <= edm::kGramLMax;
+  const int64_t g_ld = edm::gram_ld(Lx_max);
+  // Filter norms and centring constant of one library (chosen form).
+  const size_t per_lib_gram =
+      gram ? align_up(sizeof(uint32_t) * static_cast<size_t>(edm::kGramNE) * g_ld + sizeof(float), 256) : 0;
   size_t per_lib_max = 0;
   std::vector<size_t> off_E(EDM_E_MAX + 1, 0);
   for (int e = 1; e <= EDM_E_MAX; ++e) {
@@ -336,11 +398,13 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
     }
   }
   const size_t limit = workspace_limit();
-  if (per_lib_max > 0 && off_tbl + per_lib_max > limit)
+  if (per_lib_max > 0 && off_tbl + per_lib_max + per_lib_gram > limit)
     return set_err(ctx, EDM_E_NOMEM, "one library table exceeds EDM_WORKSPACE_LIMIT");
   int64_t batch = Nl;
-  if (per_lib_max > 0) batch = std::min<int64_t>(Nl, static_cast<int64_t>((limit - off_tbl) / per_lib_max));
-  EDM_RC(ws_reserve(ctx, off_tbl + per_lib_max * static_cast<size_t>(batch) + 256));
+  if (per_lib_max > 0)
+    batch = std::min<int64_t>(Nl, static_cast<int64_t>((limit - off_tbl) / (per_lib_max + per_lib_gram)));
+  const size_t off_g = off_tbl + per_lib_max * static_cast<size_t>(batch);
+  EDM_RC(ws_reserve(ctx, off_g + per_lib_gram * static_cast<size_t>(batch) + 256));
 
   std::vector<char> blob(small_bytes, 0);
   std::memcpy(blob.data() + off_Lx, Lx, sizeof(int64_t) * Nl);
@@ -389,6 +453,14 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
         a.idxE[e] = reinterpret_cast<int32_t *>(base);
         a.wE[e] = reinterpret_cast<float *>(base + sizeof(int32_t) * stride * batch);
         a.strideE[e] = stride;
+      }
+      bool gram_b = false;
+      for (int e = edm::kGramEMin; e <= EDM_E_MAX; ++e) gram_b |= gram && ((need >> (e - 1)) & 1u);
+      if (gram_b) {
+        a.gram_mu = reinterpret_cast<float *>(ctx->ws + off_g);
+        a.gram_nrm = reinterpret_cast<uint32_t *>(ctx->ws + align_up(off_g + sizeof(float) * batch, 256));
+        a.gram_ld = g_ld;
+        EDM_HIP(ctx, edm::launch_gram_prep(a, static_cast<int>(nb), L_b, ctx->stream));
       }
       EDM_HIP(ctx, edm::launch_sweep_multi(a, static_cast<int>(nb), L_b, ctx->stream));
       for (int e = 1; e <= EDM_E_MAX; ++e) {
@@ -497,6 +569,18 @@ int edm_net_forward(edm_ctx *ctx, const float *params, int32_t C, const float *X
   if (B == 0) return EDM_OK;
   EDM_RC(net_ws(ctx, C, B, L));
   EDM_HIP(ctx, edm::net_forward(params, C, X, B, L, ldx, reinterpret_cast<float *>(ctx->ws), logits, ctx->stream));
+  return EDM_OK;
+}
+
+int edm_net_forward_bf16(edm_ctx *ctx, const float *params, int32_t C, const float *X, int64_t B,
+                         int64_t L, int64_t ldx, float *logits) {
+  EDM_RC(check_net(ctx, params, C, X, B, L, ldx));
+  if (C != 32 && C != 64) return set_err(ctx, EDM_E_ARG, "the BF16 forward needs C = 32 or 64");
+  if (B > 0 && !logits) return set_err(ctx, EDM_E_ARG, "NULL logits");
+  EDM_RC(check_ctx(ctx));
+  if (B == 0) return EDM_OK;
+  EDM_RC(net_ws(ctx, C, B, L));
+  EDM_HIP(ctx, edm::net_forward_bf16(params, C, X, B, L, ldx, reinterpret_cast<float *>(ctx->ws), logits, ctx->stream));
   return EDM_OK;
 }
 

@@ -1,0 +1,557 @@
+// Chosen form of the distance step for E >= 9: a BF16 matrix-core Gram
+// filter with an exact re-rank (kEDM paper: Section 2.1 steps 1-4 and
+// Algorithms 1-2 define what is computed; the filter is this library's own
+// design for gfx950).
+//
+// Arithmetic
+// ----------
+// With centred samples b = x - mu (mu: one float32 constant per series), the
+// squared distance of query p and candidate q at dimension E is
+//     N_E(p) + N_E(q) - 2 G_E(p, q),
+// N_E the squared norm of a point's E samples and G_E their lag-wise dot
+// product.  G is a matrix product over the lag index, so the matrix cores
+// evaluate it for a 32 x 32 tile of (candidate, query) pairs per
+// v_mfma_f32_32x32x16_bf16.  Each centred sample is split into two BF16
+// numbers, b = hi + lo + r with |r| <= 2^-16 |b|, and hi*hi' + hi*lo' + lo*hi'
+// (three MFMAs, FP32 accumulation) gives G with an error below
+// 6.1 * 2^-16 |v_p| |v_q| plus the FP32 accumulation error.  The candidate's
+// norm rides along in a spare slot of the contraction (operand value one on
+// the query side), so one instruction chain yields
+//     D = s N_E(q) - 2 G_E(p, q),        s = 1 - 2^-12,
+// and the query side compares D with T = kth_E(p) - s N_E(p).  D <= T is
+// K(p, q) minus a margin 2^-12 (N_E(p) + N_E(q)) (at least three times every
+// rounding above, the canonical key's own rounding and the centring included)
+// compared with the k-th key, so a candidate that fails the test has an exact
+// key above the query's current k-th key and cannot enter its list.  Every
+// candidate that passes ("survivor") is re-ranked with the exact float32 key
+// of Algorithm 1 (lag order, one rounding per operation, contraction off) and
+// offered to the same sorted register lists as the exact scan.  Estimates
+// that are NaN pass (the test is written !(D > T)), and a series with
+// |x - mu| above 2^56 switches the filter off (T = +inf), so the result does
+// not depend on the filter: the tables and correlations are bit-identical to
+// the exact scan's.
+//
+// Layout on the chip
+// ------------------
+// * Workgroup = 8 waves = the 256 queries of one exact-scan block; the series
+//   is staged in LDS three times: float32 samples (exact re-rank, weights) and
+//   the BF16 hi and lo halves of the centred samples (matrix operands).
+// * A wave owns 32 queries.  MFMA operand A holds 32 candidates (tile rows),
+//   operand B the wave's 32 queries (tile columns, fixed for the whole scan),
+//   so lane l ends with the 16 estimates of candidates 8(v/4) + 4(l/32) + v%4
+//   for query l%32: one threshold register per E and lane.  The two lanes of a
+//   query (l and l+32) keep top-k lists over their own half of the
+//   candidates, each in ascending q, and merge them with a lexicographic
+//   (key, index) insertion at the end.
+// * K-slots of the contraction: lags 0..E_hi-1, then one norm slot per E of
+//   the group, then zeros.  A group fits one 16-slot chunk (E_hi + |group| <=
+//   16), or for E >= 16 a shared chunk of lags 0..15 plus one chunk per E.
+// * Survivors of a tile: the lanes walk their bits under a wave-uniform loop;
+//   the exact key of a survivor costs E_hi LDS reads and 3 E_hi VALU ops.
+#include <cstdint>
+
+#include "../../include/edm.h"
+#include "device_common.h"
+#include "kernels.h"
+#include "scan_common.h"
+
+#pragma clang fp contract(off)
+
+namespace edm {
+namespace {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kGramWaves = 8;
+constexpr int kGramThreads = kGramWaves * kWave;
+static_assert(kGramWaves * 32 == kKnnThreads, "a workgroup covers one query block of the exact scan");
+constexpr float kGramScale = 1.0f - 0x1p-12f;  // s = 1 - 2^-12
+constexpr float kGramFloor = 0x1p-90f;          // absolute slack: flushed tiny products
+constexpr float kGramSafeMax = 0x1p56f;         // larger |x - mu| switches the filter off
+
+__device__ __forceinline__ uint32_t bf16_bits(float f) {  // round to nearest even (finite f)
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_val(uint32_t b) { return __uint_as_float(b << 16); }
+// hi | lo << 16 with v = hi + lo to 2^-16 relative.
+__device__ __forceinline__ uint32_t split_pack(float v) {
+  const uint32_t hi = bf16_bits(v);
+  return hi | (bf16_bits(v - bf16_val(hi)) << 16);
+}
+__device__ __forceinline__ float unpack_sum(uint32_t w) {
+  return bf16_val(w & 0xffffu) + bf16_val(w >> 16);
+}
+// Both BF16 halves of a word times -2 (exact).
+__device__ __forceinline__ uint32_t scale_m2(uint32_t w) {
+  return bf16_bits(-2.0f * bf16_val(w & 0xffffu)) | (bf16_bits(-2.0f * bf16_val(w >> 16)) << 16);
+}
+
+// Eight consecutive BF16 values starting at element `base` of a 16-bit array
+// viewed as words: aligned word reads and a funnel shift for odd starts.
+__device__ __forceinline__ void read_window(const uint32_t *__restrict__ w32, int base,
+                                            uint32_t (&out)[4]) {
+  const int w0 = base >> 1;
+  const uint32_t sh = static_cast<uint32_t>(base & 1) * 16u;
+  uint32_t W[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) W[i] = w32[w0 + i];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) out[i] = __builtin_amdgcn_alignbit(W[i + 1], W[i], sh);
+}
+
+__device__ __forceinline__ f32x16_t mfma(const uint32_t (&a)[4], const uint32_t (&b)[4],
+                                         f32x16_t c) {
+  const u32x4_t av = {a[0], a[1], a[2], a[3]};
+  const u32x4_t bv = {b[0], b[1], b[2], b[3]};
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, av),
+                                                 __builtin_bit_cast(bf16x8_t, bv), c, 0, 0, 0);
+}
+
+template <int ELO, int EHI>
+struct Layout {
+  static constexpr int kLo = ELO;
+  static constexpr int NG = EHI - ELO + 1;
+  static constexpr bool kShared = ELO >= 16;  // chunk 0 = lags 0..15, the same for every E
+  static constexpr int kChunks = (EHI + NG + 15) / 16;
+  static constexpr int kFirst = kShared ? 1 : 0;  // first chunk that depends on E
+  static_assert(ELO >= kGramEMin && EHI <= EDM_E_MAX && ELO <= EHI, "E range");
+  static_assert(kShared ? kChunks == 2 : kChunks == 1, "E range does not fit the slot layout");
+  // 0: zero slot, 1: lag s, 2 + g: norm slot of E = ELO + g
+  static constexpr int kind(int s) { return s < EHI ? 1 : (s < EHI + NG ? 2 + (s - EHI) : 0); }
+};
+
+// Candidate-side words of chunk C: lane half h1 holds slots 16C + 8h1 .. +7.
+template <class Lay, int C>
+__device__ __forceinline__ void build_a(uint32_t (&ah)[4], uint32_t (&al)[4],
+                                        const uint32_t (&wh)[4], const uint32_t (&wl)[4],
+                                        const uint32_t (&nr)[Lay::NG], bool h1) {
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    uint32_t vh[2], vl[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int s0 = 16 * C + 8 * hh + 2 * w;
+      const int k0 = Lay::kind(s0), k1 = Lay::kind(s0 + 1);
+      uint32_t h = 0, l = 0;
+      if (k0 == 1) {
+        h = wh[w] & 0xffffu;
+        l = wl[w] & 0xffffu;
+      } else if (k0 >= 2) {
+        h = nr[k0 - 2] & 0xffffu;
+        l = nr[k0 - 2] >> 16;
+      }
+      if (k1 == 1) {
+        h |= wh[w] & 0xffff0000u;
+        l |= wl[w] & 0xffff0000u;
+      } else if (k1 >= 2) {
+        h |= nr[k1 - 2] << 16;
+        l |= nr[k1 - 2] & 0xffff0000u;
+      }
+      vh[hh] = h;
+      vl[hh] = l;
+    }
+    ah[w] = h1 ? vh[1] : vh[0];
+    al[w] = h1 ? vl[1] : vl[0];
+  }
+}
+
+// Query-side words of chunk C for dimension E: lags below E (already scaled
+// by -2), one in E's norm slot (hi operand only), zeros elsewhere.
+template <class Lay, int C, int E>
+__device__ __forceinline__ void build_b(uint32_t (&bh)[4], uint32_t (&bl)[4],
+                                        const uint32_t (&qh)[4], const uint32_t (&ql)[4],
+                                        bool h1) {
+  constexpr uint32_t kOne = 0x3f80u;  // BF16 1.0
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    uint32_t vh[2], vl[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int s0 = 16 * C + 8 * hh + 2 * w;
+      uint32_t h = 0, l = 0;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int s = s0 + u;
+        const int k = Lay::kind(s);
+        const uint32_t m = u ? 0xffff0000u : 0xffffu;
+        if (k == 1 && s < E) {
+          h |= qh[w] & m;
+          l |= ql[w] & m;
+        } else if (k >= 2 && k - 2 == E - Lay::kLo) {
+          h |= u ? (kOne << 16) : kOne;
+        }
+      }
+      vh[hh] = h;
+      vl[hh] = l;
+    }
+    bh[w] = h1 ? vh[1] : vh[0];
+    bl[w] = h1 ? vl[1] : vl[0];
+  }
+}
+
+// Insertion of a partner-list entry: lexicographic on (key, index) with the
+// index compared unsigned, so empty entries (index -1) sort last.
+template <int OFF, int K, int TOT>
+__device__ __forceinline__ void slice_insert_lex(float (&qk)[TOT], int (&qi)[TOT], float key, int q) {
+  const uint32_t uq = static_cast<uint32_t>(q);
+#pragma unroll
+  for (int i = K - 1; i > 0; --i) {
+    const bool lt_prev = key < qk[OFF + i - 1] ||
+                         (key == qk[OFF + i - 1] && uq < static_cast<uint32_t>(qi[OFF + i - 1]));
+    const bool lt_cur =
+        key < qk[OFF + i] || (key == qk[OFF + i] && uq < static_cast<uint32_t>(qi[OFF + i]));
+    qi[OFF + i] = lt_prev ? qi[OFF + i - 1] : (lt_cur ? q : qi[OFF + i]);
+    qk[OFF + i] = lt_prev ? qk[OFF + i - 1] : (lt_cur ? key : qk[OFF + i]);
+  }
+  const bool lt0 = key < qk[OFF] || (key == qk[OFF] && uq < static_cast<uint32_t>(qi[OFF]));
+  qi[OFF] = lt0 ? q : qi[OFF];
+  qk[OFF] = lt0 ? key : qk[OFF];
+}
+
+// One workgroup's share of a filtered scan: query block `bx` of row `row`,
+// every E in [ELO, EHI].  Same outputs as the exact group scan.
+template <int ELO, int EHI>
+__device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const int bx,
+                                          float *__restrict__ smem) {
+  using Lay = Layout<ELO, EHI>;
+  constexpr int NG = Lay::NG;
+  constexpr int TOT = list_off<ELO>(EHI + 1);
+  constexpr int NCH = Lay::kChunks;
+  constexpr int C0 = Lay::kFirst;
+  __shared__ Mom wmom[kGramWaves][NG];
+  const uint32_t need = a.need_dev ? a.need_dev[row] : a.need;
+  const float *__restrict__ x = a.X + static_cast<int64_t>(row) * a.ldx;
+  const int L = static_cast<int>(a.L_dev ? a.L_dev[row] : a.L_uni);
+  const int Tp = a.Tp;
+  const int m_lo = L - (ELO - 1) - Tp;  // queries = candidates at ELO, the widest range
+  if (m_lo - 1 < ELO + 1) return;
+  const int blk0 = bx * kKnnThreads;
+  if (blk0 >= m_lo) return;
+
+  const int64_t ld = a.gram_ld;
+  float *xs = smem;
+  uint16_t *xh = reinterpret_cast<uint16_t *>(smem + ld);
+  uint16_t *xl = xh + ld;
+  const uint32_t *xh32 = reinterpret_cast<const uint32_t *>(xh);
+  const uint32_t *xl32 = reinterpret_cast<const uint32_t *>(xl);
+  const float mu = a.gram_mu[row];
+  const uint32_t *__restrict__ nrm =
+      a.gram_nrm + (static_cast<int64_t>(row) * kGramNE + (ELO - kGramEMin)) * ld;
+
+  bool bad = false, big = false;
+  for (int i = threadIdx.x; i < L + kGramPad; i += kGramThreads) {
+    float v = 0.0f, b = 0.0f;
+    if (i < L) {
+      v = x[i];
+      bad |= !isfinite(v);
+      b = v - mu;
+    }
+    big |= !(fabsf(b) <= kGramSafeMax);
+    xs[i] = v;
+    const uint32_t pk = split_pack(b);
+    xh[i] = static_cast<uint16_t>(pk & 0xffffu);
+    xl[i] = static_cast<uint16_t>(pk >> 16);
+  }
+  if (bad) atomicOr(a.status, 1);
+  const bool unsafe = __syncthreads_or(big);
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int n = lane & 31;
+  const bool h1 = lane >= 32;
+  const int wave = threadIdx.x / kWave;
+  const int pw = __builtin_amdgcn_readfirstlane(blk0 + 32 * wave);
+  const int p = pw + n;
+  const bool qry = p < m_lo;
+  const int pc = qry ? p : 0;
+
+  float vp[EHI];
+#pragma unroll
+  for (int j = 0; j < EHI; ++j) vp[j] = qry ? xs[p + j] : 0.0f;
+
+  float qk[TOT];
+  int qi[TOT];
+  static_for<ELO, EHI>([&](auto EC) {
+    constexpr int E = decltype(EC)::value;
+    constexpr int OFF = list_off<ELO>(E);
+    const bool act = p < L - (E - 1) - Tp && (a.mom != nullptr || ((need >> (E - 1)) & 1u));
+#pragma unroll
+    for (int i = 0; i < E + 1; ++i) {
+      qk[OFF + i] = act ? __builtin_inff() : -1.0f;
+      qi[OFF + i] = -1;
+    }
+  });
+
+  // Query norms s N_E(p) and the thresholds T_E = kth_E - s N_E(p).
+  float nq[NG], thr[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) nq[g] = unpack_sum(nrm[g * ld + pc]);
+  auto refresh = [&]() {
+    static_for<ELO, EHI>([&](auto EC) {
+      constexpr int E = decltype(EC)::value;
+      const float kth = qk[list_off<ELO>(E) + E];
+      thr[E - ELO] = kth < 0.0f ? -__builtin_inff()
+                                : (unsafe ? __builtin_inff() : (kth - nq[E - ELO]) + kGramFloor);
+    });
+  };
+  refresh();
+
+  // Query operands (fixed for the scan).
+  uint32_t bsh[4], bsl[4];
+  uint32_t bh[NG][NCH - C0][4], bl[NG][NCH - C0][4];
+  static_for<0, NCH - 1>([&](auto CC) {
+    constexpr int C = decltype(CC)::value;
+    uint32_t qh[4], ql[4];
+    read_window(xh32, pc + 16 * C + (h1 ? 8 : 0), qh);
+    read_window(xl32, pc + 16 * C + (h1 ? 8 : 0), ql);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      qh[w] = scale_m2(qh[w]);
+      ql[w] = scale_m2(ql[w]);
+    }
+    if constexpr (Lay::kShared && C == 0) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        bsh[w] = qh[w];
+        bsl[w] = ql[w];
+      }
+    } else {
+      static_for<ELO, EHI>([&](auto EC) {
+        constexpr int E = decltype(EC)::value;
+        build_b<Lay, C, E>(bh[E - ELO][C - C0], bl[E - ELO][C - C0], qh, ql, h1);
+      });
+    }
+  });
+
+  if (pw < m_lo) {
+#pragma unroll 1
+    for (int c0 = 0; c0 < m_lo; c0 += 32) {
+      const int qa = c0 + n;  // candidate of the A rows this lane supplies
+      uint32_t nr[NG];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) nr[g] = nrm[g * ld + qa];
+      uint32_t ah[NCH][4], al[NCH][4];
+      static_for<0, NCH - 1>([&](auto CC) {
+        constexpr int C = decltype(CC)::value;
+        uint32_t wh[4], wl[4];
+        read_window(xh32, qa + 16 * C + (h1 ? 8 : 0), wh);
+        read_window(xl32, qa + 16 * C + (h1 ? 8 : 0), wl);
+        build_a<Lay, C>(ah[C], al[C], wh, wl, nr, h1);
+      });
+      f32x16_t acc_s = {};
+      if constexpr (Lay::kShared) {
+        acc_s = mfma(ah[0], bsh, acc_s);
+        acc_s = mfma(ah[0], bsl, acc_s);
+        acc_s = mfma(al[0], bsh, acc_s);
+      }
+      bool surv[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) surv[v] = false;
+      static_for<ELO, EHI>([&](auto EC) {
+        constexpr int g = decltype(EC)::value - ELO;
+        f32x16_t acc = acc_s;
+#pragma unroll
+        for (int C = C0; C < NCH; ++C) {
+          acc = mfma(ah[C], bh[g][C - C0], acc);
+          acc = mfma(ah[C], bl[g][C - C0], acc);
+          acc = mfma(al[C], bh[g][C - C0], acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) surv[v] = surv[v] || !(acc[v] > thr[g]);
+      });
+      bool any = false;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) any = any || surv[v];
+      if (__builtin_amdgcn_ballot_w64(any)) {
+        uint32_t bits = 0;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) bits |= surv[v] ? (1u << v) : 0u;
+#pragma unroll 1
+        while (__builtin_amdgcn_ballot_w64(bits != 0u)) {
+          const bool has = bits != 0u;
+          const int v = has ? __builtin_ctz(bits) : 0;
+          bits &= bits - 1u;
+          const int q = c0 + 8 * (v >> 2) + (h1 ? 4 : 0) + (v & 3);
+          const bool ok = has && q != p;
+          float acc = 0.0f;
+          float key[NG];
+          static_for<0, EHI - 1>([&](auto JC) {
+            constexpr int j = decltype(JC)::value;
+            const float d = vp[j] - xs[q + j];
+            acc = acc + d * d;
+            if constexpr (j + 1 >= ELO) key[j + 1 - ELO] = acc;
+          });
+          static_for<ELO, EHI>([&](auto EC) {
+            constexpr int E = decltype(EC)::value;
+            slice_offer<list_off<ELO>(E), E + 1, TOT>(qk, qi, key[E - ELO], q,
+                                                      ok && q < L - (E - 1) - Tp);
+          });
+        }
+        refresh();
+      }
+    }
+  }
+
+  // Each query's two half-lists -> its full list (both lanes end equal).
+  static_for<ELO, EHI>([&](auto EC) {
+    constexpr int E = decltype(EC)::value;
+    constexpr int OFF = list_off<ELO>(E);
+    float pk[E + 1];
+    int pi[E + 1];
+#pragma unroll
+    for (int i = 0; i < E + 1; ++i) {
+      pk[i] = __shfl_xor(qk[OFF + i], 32);
+      pi[i] = __shfl_xor(qi[OFF + i], 32);
+    }
+#pragma unroll
+    for (int i = 0; i < E + 1; ++i) slice_insert_lex<OFF, E + 1, TOT>(qk, qi, pk[i], pi[i]);
+  });
+
+  // Epilogue: E alternates between the two lanes of a query.  The co-moments
+  // are merged in the order of the exact scan (a 32-lane butterfly per half,
+  // then the two halves of each 64-query group, then the groups in order), so
+  // the correlations match it bit for bit.
+  static_for<ELO, EHI>([&](auto EC) {
+    constexpr int E = decltype(EC)::value;
+    constexpr int g = E - ELO;
+    const bool own = h1 == ((g & 1) != 0);
+    Mom mine = mom_zero();
+    if (own) mine = finish_list<E, list_off<ELO>(E), TOT, EHI>(a, row, p, L, Tp, need, vp, qi, xs);
+    if (a.mom) {  // uniform
+#pragma unroll
+      for (int m = 1; m < 32; m <<= 1) mine = mom_merge(mine, mom_shfl_xor(mine, m));
+      if (lane == ((g & 1) ? 32 : 0)) wmom[wave][g] = mine;
+    }
+  });
+  if (a.mom == nullptr) return;
+  __syncthreads();
+  if (static_cast<int>(threadIdx.x) < NG) {
+    const int g = static_cast<int>(threadIdx.x);
+    const int E = ELO + g;
+    const int mE = L - (E - 1) - Tp;
+    if (mE - 1 >= E + 1 && blk0 < mE) {
+      Mom t = mom_merge(wmom[0][g], wmom[1][g]);
+#pragma unroll
+      for (int w = 1; w < kGramWaves / 2; ++w) t = mom_merge(t, mom_merge(wmom[2 * w][g], wmom[2 * w + 1][g]));
+      a.mom[(static_cast<int64_t>(row) * a.E_max + (E - 1)) * a.mom_blocks + bx] = t;
+    }
+  }
+}
+
+template <int ELO, int EHI>
+__global__ __launch_bounds__(kGramThreads) void k_gram(KnnArgs a, int slot0) {
+  extern __shared__ float gram_smem[];
+  gram_scan<ELO, EHI>(a, slot0 + static_cast<int>(blockIdx.y), static_cast<int>(blockIdx.x),
+                      gram_smem);
+}
+
+// Centring constant of each slot: the float32 mean (float64 sum).
+__global__ __launch_bounds__(256) void k_gram_mean(KnnArgs a) {
+  const int row = static_cast<int>(blockIdx.x);
+  const float *__restrict__ x = a.X + static_cast<int64_t>(row) * a.ldx;
+  const int64_t L = a.L_dev ? a.L_dev[row] : a.L_uni;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < L; i += 256) s += static_cast<double>(x[i]);
+  for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m);
+  __shared__ double part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = (part[0] + part[1]) + (part[2] + part[3]);
+    a.gram_mu[row] = L > 0 ? static_cast<float>(t / static_cast<double>(L)) : 0.0f;
+  }
+}
+
+// Packed s N_E(q) for every E >= kGramEMin and q < gram_ld (zero samples past
+// the end of the series).
+__global__ __launch_bounds__(256) void k_gram_norms(KnnArgs a) {
+  const int row = static_cast<int>(blockIdx.y);
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t ld = a.gram_ld;
+  if (q >= ld) return;
+  const float *__restrict__ x = a.X + static_cast<int64_t>(row) * a.ldx;
+  const int64_t L = a.L_dev ? a.L_dev[row] : a.L_uni;
+  const float mu = a.gram_mu[row];
+  uint32_t *out = a.gram_nrm + static_cast<int64_t>(row) * kGramNE * ld + q;
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < EDM_E_MAX; ++j) {
+    const float b = q + j < L ? x[q + j] - mu : 0.0f;
+    s = s + b * b;
+    if (j + 1 >= kGramEMin) out[(j + 1 - kGramEMin) * ld] = split_pack(kGramScale * s);
+  }
+}
+
+using GramFn = void (*)(KnnArgs, int);
+
+template <int LO, int HI>
+constexpr GramFn gram_fn() {
+  return &k_gram<LO, HI>;
+}
+
+// (lo, hi) -> kernel; lo is a group start of the filtered partition.
+GramFn pick(int lo, int hi) {
+  switch (lo) {
+    case 9: {
+      constexpr GramFn t[] = {gram_fn<9, 9>(), gram_fn<9, 10>(), gram_fn<9, 11>(), gram_fn<9, 12>()};
+      return hi >= 9 && hi <= 12 ? t[hi - 9] : nullptr;
+    }
+    case 13: {
+      constexpr GramFn t[] = {gram_fn<13, 13>(), gram_fn<13, 14>()};
+      return hi >= 13 && hi <= 14 ? t[hi - 13] : nullptr;
+    }
+    case 15:
+      return hi == 15 ? gram_fn<15, 15>() : nullptr;
+    case 16: {
+      constexpr GramFn t[] = {gram_fn<16, 16>(), gram_fn<16, 17>(), gram_fn<16, 18>()};
+      return hi >= 16 && hi <= 18 ? t[hi - 16] : nullptr;
+    }
+    case 19: {
+      constexpr GramFn t[] = {gram_fn<19, 19>(), gram_fn<19, 20>()};
+      return hi >= 19 && hi <= 20 ? t[hi - 19] : nullptr;
+    }
+    default:
+      return nullptr;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gram_prep(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t st) {
+  if (nslots <= 0) return hipSuccess;
+  if (a.gram_ld < L_max + kGramPad) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gram_mean, dim3(static_cast<unsigned>(nslots)), dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned gx = static_cast<unsigned>((a.gram_ld + 255) / 256);
+  hipLaunchKernelGGL(k_gram_norms, dim3(gx, static_cast<unsigned>(nslots)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_group(const KnnArgs &a, int lo, int hi, int nslots, int64_t L_max,
+                             hipStream_t st) {
+  if (nslots <= 0) return hipSuccess;
+  const GramFn fn = pick(lo, hi);
+  if (fn == nullptr || L_max > kGramLMax || a.gram_ld < L_max + kGramPad || a.tau != 1)
+    return hipErrorInvalidValue;
+  const size_t shm = static_cast<size_t>(a.gram_ld) * (sizeof(float) + 2 * sizeof(uint16_t));
+  const void *f = reinterpret_cast<const void *>(fn);
+  if (shm > 65536) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(shm));
+    if (e != hipSuccess) return e;
+  }
+  const unsigned gx = static_cast<unsigned>((L_max + kKnnThreads - 1) / kKnnThreads);
+  constexpr int kMaxY = 32768;
+  for (int s0 = 0; s0 < nslots; s0 += kMaxY) {
+    const int ny = nslots - s0 < kMaxY ? nslots - s0 : kMaxY;
+    hipLaunchKernelGGL(fn, dim3(gx, static_cast<unsigned>(ny)), dim3(kGramThreads), shm, st, a, s0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace edm

@@ -45,6 +45,13 @@ struct KnnArgs {
   const int64_t *tbl_off;
   int32_t *tbl_idx;
   float *tbl_w;
+  // Matrix-core filter (chosen form, E >= kGramEMin): per-slot centring
+  // constants and packed BF16 hi/lo norms, [slot][E - kGramEMin][gram_ld]
+  // (written by launch_gram_prep).  gram_nrm == nullptr selects the exact
+  // scan for every E.
+  float *gram_mu;
+  uint32_t *gram_nrm;
+  int64_t gram_ld;
 };
 
 // Work item of the persistent table kernel: E group and query block of a row.
@@ -71,6 +78,21 @@ struct LookupItem {
 hipError_t launch_tables_persistent(const KnnArgs &a, int group, const TableItem *items,
                                     int n_items, int *counter, int64_t L_max, int wg_per_cu,
                                     int n_cu, hipStream_t st);
+
+// Matrix-core filter of the batched scans (gram.hip).  E values from
+// kGramEMin up run through it when KnnArgs::gram_nrm is set; kGramLMax bounds
+// the series length (LDS holds the series three times).
+constexpr int kGramEMin = 9;
+constexpr int kGramNE = EDM_E_MAX - kGramEMin + 1;
+constexpr int kGramPad = 64;  // zero samples staged past the end of a series
+constexpr int64_t kGramLMax = 16384;
+inline int64_t gram_ld(int64_t L_max) { return (L_max + kGramPad + 63) / 64 * 64; }
+// Per slot: centring constant, then the packed norms of every E >= kGramEMin.
+hipError_t launch_gram_prep(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t st);
+// Batched scan of one E range [lo, hi] (lo >= kGramEMin) through the filter;
+// same outputs as launch_sweep_multi.
+hipError_t launch_gram_group(const KnnArgs &a, int lo, int hi, int nslots, int64_t L_max,
+                             hipStream_t st);
 
 // Launch the kNN kernel for `nslots` libraries whose longest series has
 // `L_max` samples.  Returns a hipError_t.

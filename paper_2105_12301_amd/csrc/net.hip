@@ -113,6 +113,107 @@ __global__ __launch_bounds__(256) void k_conv(const float *__restrict__ x, int64
   }
 }
 
+// ---- BF16 inference form of the C -> C convolutions (matrix cores) --------
+// The contraction over (tap k, input channel i) runs as a GEMM on
+// v_mfma_f32_32x32x16_bf16: A = weights [co][k*C + i] (BF16), B = the input
+// window [k*C + i][t] = x[i][t + k - HALO] (BF16), FP32 accumulation.  One
+// workgroup = one series x 256 time steps x all C output channels; the input
+// window is staged in LDS transposed to [t][i] so every lane's eight K values
+// (eight consecutive channels at one tap) are one aligned 16-byte read, and
+// the weights are staged as [co][k][i].  Wave w owns time tiles 2w, 2w+1 and
+// every output-channel tile.  Rows are padded by 8 BF16 values (16 bytes)
+// against LDS bank conflicts.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+constexpr int TB = 256;  // time steps per workgroup of the BF16 convolution
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {  // round to nearest even (finite f)
+  const uint32_t u = __float_as_uint(f);
+  return static_cast<uint16_t>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// w[co][ci][k] float32 -> wb[co][k][ci] BF16.
+__global__ void k_w_to_bf16(const float *__restrict__ w, int C, uint16_t *__restrict__ wb) {
+  const int i = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= C * C * KW) return;
+  const int co = i / (KW * C), r = i - co * (KW * C);
+  const int k = r / C, ci = r - k * C;
+  wb[i] = to_bf16(w[(co * C + ci) * KW + k]);
+}
+
+template <int C>
+constexpr size_t conv_bf16_lds() {
+  return sizeof(uint16_t) * ((TB + KW - 1) * (C + 8) + C * (KW * C + 8));
+}
+
+// y = relu(conv(x, w) + b) for x, y [B][C][L] float32 (inputs rounded to BF16).
+template <int C>
+__global__ __launch_bounds__(256) void k_conv_bf16(const float *__restrict__ x, int L,
+                                                   const uint16_t *__restrict__ wb,
+                                                   const float *__restrict__ bias,
+                                                   float *__restrict__ y) {
+  static_assert(C % 32 == 0 && C <= 64, "C must be 32 or 64");
+  constexpr int XR = TB + KW - 1, XS = C + 8, WR = KW * C, WS = WR + 8;
+  constexpr int NCO = C / 32, NCC = C / 16;
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds_bf16[];
+  uint16_t *xs = lds_bf16;
+  uint16_t *ws = lds_bf16 + XR * XS;
+  const int b = blockIdx.y;
+  const int t0 = blockIdx.x * TB;
+  const int tid = threadIdx.x;
+  const float *xb = x + static_cast<int64_t>(b) * C * L;
+  for (int e = tid; e < C * WR; e += 256) {
+    const int co = e / WR, r = e - co * WR;
+    ws[co * WS + r] = wb[e];
+  }
+  for (int e = tid; e < C * XR; e += 256) {
+    const int ci = e / XR, t = e - ci * XR;
+    const int tg = t0 + t - HALO;
+    const float v = (tg >= 0 && tg < L) ? xb[static_cast<int64_t>(ci) * L + tg] : 0.0f;
+    xs[t * XS + ci] = to_bf16(v);
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63, n = lane & 31, h = lane >> 5;
+  f32x16_t acc[2][NCO];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int c = 0; c < NCO; ++c) acc[j][c] = f32x16_t{};
+#pragma unroll 1
+  for (int k = 0; k < KW; ++k) {
+#pragma unroll
+    for (int cc = 0; cc < NCC; ++cc) {
+      bf16x8_t bop[2], aop[NCO];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int tl = 64 * wave + 32 * j + n;
+        bop[j] = *reinterpret_cast<const bf16x8_t *>(xs + (tl + k) * XS + 16 * cc + 8 * h);
+      }
+#pragma unroll
+      for (int c = 0; c < NCO; ++c)
+        aop[c] = *reinterpret_cast<const bf16x8_t *>(ws + (32 * c + n) * WS + k * C + 16 * cc + 8 * h);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int c = 0; c < NCO; ++c)
+          acc[j][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[c], bop[j], acc[j][c], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int t = t0 + 64 * wave + 32 * j + n;
+    if (t >= L) continue;
+#pragma unroll
+    for (int c = 0; c < NCO; ++c)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int co = 32 * c + 8 * (v >> 2) + 4 * h + (v & 3);
+        y[(static_cast<int64_t>(b) * C + co) * L + t] = fmaxf(acc[j][c][v] + bias[co], 0.0f);
+      }
+  }
+}
+
 // Partial weight gradients of one slice of (series, time):
 // part[s][o][i][k] = sum over the slice of dz[b][o][t] * x[b][i][t + k - HALO],
 // part_b[s][o] = sum over the slice of dz[b][o][t] (from the i-chunk-0 blocks).
@@ -400,6 +501,41 @@ hipError_t net_forward(const float *theta, int C, const float *X, int64_t B, int
   hipLaunchKernelGGL(k_conv<0>, grid, dim3(256), 0, st, X, ldx, 0, 1, C, static_cast<int>(L), P.w1, P.b1, nullptr, a1);
   hipLaunchKernelGGL(k_conv<0>, grid, dim3(256), 0, st, a1, C * L, L, C, C, static_cast<int>(L), P.w2, P.b2, nullptr, a2);
   hipLaunchKernelGGL(k_conv<0>, grid, dim3(256), 0, st, a2, C * L, L, C, C, static_cast<int>(L), P.w3, P.b3, nullptr, a3);
+  hipLaunchKernelGGL(k_pool_linear, dim3(static_cast<unsigned>(B)), dim3(256), 0, st, a3, C, static_cast<int>(L), P.wo, P.bo, g, logits);
+  return hipGetLastError();
+}
+
+template <int C>
+hipError_t conv_bf16_layer(const float *in, int64_t B, int64_t L, const uint16_t *wb,
+                           const float *bias, float *out, hipStream_t st) {
+  const void *fn = reinterpret_cast<const void *>(&k_conv_bf16<C>);
+  const size_t shm = conv_bf16_lds<C>();
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm));
+  if (e != hipSuccess) return e;
+  const dim3 grid(static_cast<unsigned>((L + TB - 1) / TB), static_cast<unsigned>(B));
+  hipLaunchKernelGGL(k_conv_bf16<C>, grid, dim3(256), shm, st, in, static_cast<int>(L), wb, bias, out);
+  return hipGetLastError();
+}
+
+hipError_t net_forward_bf16(const float *theta, int C, const float *X, int64_t B, int64_t L,
+                            int64_t ldx, float *ws, float *logits, hipStream_t st) {
+  if (C != 32 && C != 64) return hipErrorInvalidValue;
+  const NetParams P = net_params(theta, C);
+  float *a1 = ws, *a2 = a1 + B * C * L, *a3 = a2 + B * C * L;
+  float *g = a3 + B * C * L;
+  uint16_t *wb2 = reinterpret_cast<uint16_t *>(g + B * C);
+  uint16_t *wb3 = wb2 + C * C * KW;
+  const unsigned nw = static_cast<unsigned>((C * C * KW + 255) / 256);
+  hipLaunchKernelGGL(k_w_to_bf16, dim3(nw), dim3(256), 0, st, P.w2, C, wb2);
+  hipLaunchKernelGGL(k_w_to_bf16, dim3(nw), dim3(256), 0, st, P.w3, C, wb3);
+  const dim3 grid(static_cast<unsigned>((L + TT - 1) / TT), static_cast<unsigned>(B));
+  hipLaunchKernelGGL(k_conv<0>, grid, dim3(256), 0, st, X, ldx, 0, 1, C, static_cast<int>(L), P.w1, P.b1, nullptr, a1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = C == 64 ? conv_bf16_layer<64>(a1, B, L, wb2, P.b2, a2, st) : conv_bf16_layer<32>(a1, B, L, wb2, P.b2, a2, st);
+  if (e != hipSuccess) return e;
+  e = C == 64 ? conv_bf16_layer<64>(a2, B, L, wb3, P.b3, a3, st) : conv_bf16_layer<32>(a2, B, L, wb3, P.b3, a3, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pool_linear, dim3(static_cast<unsigned>(B)), dim3(256), 0, st, a3, C, static_cast<int>(L), P.wo, P.bo, g, logits);
   return hipGetLastError();
 }

@@ -22,6 +22,10 @@ int64_t net_workspace_floats(int C, int64_t B, int64_t L);
 
 hipError_t net_forward(const float *theta, int C, const float *X, int64_t B, int64_t L,
                        int64_t ldx, float *ws, float *logits, hipStream_t st);
+// Inference with the C -> C convolutions on BF16 matrix cores (C = 32 or 64);
+// uses the first 3 B C L + B C floats of ws plus 2 C C KW BF16 weights.
+hipError_t net_forward_bf16(const float *theta, int C, const float *X, int64_t B, int64_t L,
+                            int64_t ldx, float *ws, float *logits, hipStream_t st);
 hipError_t net_loss_grad(const float *theta, int C, const float *X, const int32_t *labels,
                          int64_t B, int64_t L, int64_t ldx, float *ws, float *loss,
                          float *grad, hipStream_t st);

@@ -17,12 +17,12 @@
 // co-moments reduced per block.  tau = 1 only (the sweep's lag); other lags
 // use the per-E kernel.
 #include <array>
-#include <type_traits>
 #include <utility>
 
 #include "../../include/edm.h"
 #include "device_common.h"
 #include "kernels.h"
+#include "scan_common.h"
 
 #pragma clang fp contract(off)
 
@@ -30,46 +30,6 @@ namespace edm {
 namespace {
 
 constexpr int kUnroll = 8;
-
-template <int I0, int I1, typename F>
-__device__ __forceinline__ void static_for(F &&f) {
-  if constexpr (I0 <= I1) {
-    f(std::integral_constant<int, I0>{});
-    static_for<I0 + 1, I1>(f);
-  }
-}
-
-// Offset of dimension E's list inside the flat register arrays of a group.
-template <int ELO>
-constexpr int list_off(int E) {
-  int o = 0;
-  for (int e = ELO; e < E; ++e) o += e + 1;
-  return o;
-}
-
-// Sorted insertion into the slice [OFF, OFF+K) of the flat lists; inserting
-// +inf leaves the slice unchanged (see knn.hip).
-template <int OFF, int K, int TOT>
-__device__ __forceinline__ void slice_insert(float (&qk)[TOT], int (&qi)[TOT], float key, int q) {
-#pragma unroll
-  for (int i = K - 1; i > 0; --i) {
-    const bool lt_prev = key < qk[OFF + i - 1];
-    const bool lt_cur = key < qk[OFF + i];
-    qi[OFF + i] = lt_prev ? qi[OFF + i - 1] : (lt_cur ? q : qi[OFF + i]);
-    qk[OFF + i] = __builtin_amdgcn_fmed3f(qk[OFF + i - 1], key, qk[OFF + i]);
-  }
-  const bool lt0 = key < qk[OFF];
-  qi[OFF] = lt0 ? q : qi[OFF];
-  qk[OFF] = lt0 ? key : qk[OFF];
-}
-
-template <int OFF, int K, int TOT>
-__device__ __forceinline__ void slice_offer(float (&qk)[TOT], int (&qi)[TOT], float key, int q,
-                                            bool valid) {
-  const bool want = valid && key < qk[OFF + K - 1];
-  if (__builtin_amdgcn_ballot_w64(want))
-    slice_insert<OFF, K, TOT>(qk, qi, want ? key : __builtin_inff(), q);
-}
 
 // One workgroup's share of a batched scan: query block `bx` of row `row`,
 // every E in [ELO, EHI].  Called by the grid kernel and by the persistent
@@ -197,73 +157,7 @@ __device__ __forceinline__ void group_scan(const KnnArgs &a, const int row, cons
   const int wave = threadIdx.x / kWave;
   static_for<ELO, EHI>([&](auto EC) {
     constexpr int E = decltype(EC)::value;
-    constexpr int K = E + 1;
-    constexpr int OFF = list_off<ELO>(E);
-    const int mE = L - (E - 1) - Tp;
-    Mom mine = mom_zero();
-    const bool want_table = a.mom == nullptr && ((need >> (E - 1)) & 1u);
-    if (p < mE && mE - 1 >= K && (a.mom != nullptr || want_table)) {
-      double D[K];
-      double dmin = __builtin_inf();
-#pragma unroll 1
-      for (int r = 0; r < K; ++r) {
-        const int q = qi[OFF] < 0 ? 0 : qi[OFF];
-        double s2 = 0.0;
-#pragma unroll
-        for (int j = 0; j < E; ++j) {
-          const double d = static_cast<double>(vp[j]) - static_cast<double>(xs[q + j]);
-          s2 += d * d;
-        }
-        const double dq = sqrt(s2);
-        dmin = fmin(dmin, dq);
-#pragma unroll
-        for (int i = 0; i < K - 1; ++i) {
-          qi[OFF + i] = qi[OFF + i + 1];
-          D[i] = D[i + 1];
-        }
-        qi[OFF + K - 1] = q;
-        D[K - 1] = dq;
-      }
-      double wsum = 0.0;
-#pragma unroll 1
-      for (int r = 0; r < K; ++r) {
-        const double d = D[0];
-        const double wq = dmin > 0.0 ? exp(-d / dmin) : (d == 0.0 ? 1.0 : 0.0);
-        wsum += wq;
-#pragma unroll
-        for (int i = 0; i < K - 1; ++i) D[i] = D[i + 1];
-        D[K - 1] = wq;
-      }
-      const double inv = 1.0 / wsum;
-      if (want_table) {
-        int32_t *ti;
-        float *tw;
-        int64_t base;
-        if (a.tbl_off) {
-          const int64_t o = a.tbl_off[static_cast<int64_t>(row) * (EDM_E_MAX + 1) + E];
-          ti = a.tbl_idx + o;
-          tw = a.tbl_w + o;
-          base = static_cast<int64_t>(p) * K;
-        } else {
-          ti = a.idxE[E];
-          tw = a.wE[E];
-          base = static_cast<int64_t>(row) * a.strideE[E] + static_cast<int64_t>(p) * K;
-        }
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-          ti[base + i] = qi[OFF + i];
-          tw[base + i] = static_cast<float>(D[i] * inv);
-        }
-      } else {
-        const int o_off = (E - 1) + Tp;
-        double yh = 0.0;
-#pragma unroll
-        for (int i = 0; i < K; ++i) yh += (D[i] * inv) * static_cast<double>(xs[qi[OFF + i] + o_off]);
-        mine.n = 1.0;
-        mine.mo = static_cast<double>(xs[p + o_off]);
-        mine.mp = yh;
-      }
-    }
+    const Mom mine = finish_list<E, list_off<ELO>(E), TOT, EHI>(a, row, p, L, Tp, need, vp, qi, xs);
     if (a.mom) {  // uniform
       const Mom wv = mom_wave_reduce(mine);
       if (lane == 0) wmom[wave][E - ELO] = wv;
@@ -352,15 +246,24 @@ hipError_t launch_sweep_multi(const KnnArgs &a, int nslots, int64_t L_max, hipSt
   if (nslots <= 0) return hipSuccess;
   const unsigned gx = static_cast<unsigned>((L_max + kKnnThreads - 1) / kKnnThreads);
   const size_t shm = static_cast<size_t>(L_max) * sizeof(float);
-  for (const auto &g : kGroups) {
-    const int lo = g[0];
-    int hi = g[1] < a.E_max ? g[1] : a.E_max;
+  // With the matrix-core filter, E >= kGramEMin runs in the filtered groups
+  // (their slot layout needs E_hi + |group| <= 16, or a shared first chunk).
+  constexpr int kGramGroups[][2] = {{9, 12}, {13, 14}, {15, 15}, {16, 18}, {19, 20}};
+  const bool gram = a.gram_nrm != nullptr && L_max <= kGramLMax;
+  auto hi_of = [&](int lo, int top) {
+    int hi = top < a.E_max ? top : a.E_max;
     if (a.mom == nullptr) {  // table mode: the group's scan must reach its largest needed E
       hi = 0;
-      for (int E = lo; E <= g[1]; ++E)
+      for (int E = lo; E <= top; ++E)
         if ((a.need >> (E - 1)) & 1u) hi = E;
-      if (hi == 0) continue;
     }
+    return hi;
+  };
+  for (const auto &g : kGroups) {
+    const int lo = g[0];
+    if (gram && lo >= kGramEMin) break;
+    const int hi = hi_of(lo, g[1]);
+    if (hi == 0) continue;
     if (lo > hi) break;
     const std::array<LaunchFn, 8> &t = lo == 1 ? t1 : lo == 9 ? t9 : lo == 13 ? t13 : lo == 16 ? t16 : t19;
     LaunchFn fn = t[hi - lo];
@@ -370,6 +273,15 @@ hipError_t launch_sweep_multi(const KnnArgs &a, int nslots, int64_t L_max, hipSt
       hipError_t e = fn(a, dim3(gx, static_cast<unsigned>(ny)), shm, s0, st);
       if (e != hipSuccess) return e;
     }
+  }
+  if (!gram) return hipSuccess;
+  for (const auto &g : kGramGroups) {
+    const int lo = g[0];
+    const int hi = hi_of(lo, g[1]);
+    if (hi == 0) continue;
+    if (lo > hi) break;
+    hipError_t e = launch_gram_group(a, lo, hi, nslots, L_max, st);
+    if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }

@@ -29,6 +29,7 @@ EDM_E_NOMEM = -4
 EDM_E_NONFINITE = -5
 EDM_FORM_PLAIN = 0
 EDM_FORM_CHOSEN = 1
+EDM_FORM_BATCHED = 2
 E_MAX = 20
 K_MAX = 32
 L_MAX = 32768
@@ -41,7 +42,8 @@ EXPORTS = (
     "edm_ctx_create", "edm_ctx_set_form", "edm_sync", "edm_last_error",
     "edm_ctx_destroy", "edm_embed", "edm_knn", "edm_lookup",
     "edm_simplex_sweep", "edm_ccm",
-    "edm_net_param_count", "edm_net_forward", "edm_net_loss_grad", "edm_net_adam",
+    "edm_net_param_count", "edm_net_forward", "edm_net_forward_bf16", "edm_net_loss_grad",
+    "edm_net_adam",
     "edm_select_E",
     "edm_tune_default", "edm_ccm_plan_create", "edm_ccm_plan_run", "edm_ccm_plan_destroy",
 )
@@ -94,6 +96,7 @@ def load_library(path: str = LIB_PATH):
         lib.edm_net_param_count.argtypes = [_i32]
         lib.edm_net_param_count.restype = _i64
         lib.edm_net_forward.argtypes = [_p, _p, _i32, _p, _i64, _i64, _i64, _p]
+        lib.edm_net_forward_bf16.argtypes = [_p, _p, _i32, _p, _i64, _i64, _i64, _p]
         lib.edm_net_loss_grad.argtypes = [_p, _p, _i32, _p, _p, _i64, _i64, _i64, _p, _p]
         lib.edm_net_adam.argtypes = [_p, _p, _p, _p, _p, _i64, _i32, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_float, ctypes.c_float]
@@ -302,6 +305,19 @@ def edm_net_forward(params, C: int, X, logits=None, ctx: Context | None = None):
     _check(load_library().edm_net_forward(ctx.handle, _dev_ptr(params, torch.float32, "params"), C,
                                           _dev_ptr(X, torch.float32, "X"), B, L, X.stride(0),
                                           _dev_ptr(logits, torch.float32, "logits")), ctx.handle)
+    return logits
+
+
+def edm_net_forward_bf16(params, C: int, X, logits=None, ctx: Context | None = None):
+    """Inference logits float32 [B][20] with the C -> C convolutions on BF16
+    matrix cores (C = 32 or 64)."""
+    ctx = ctx or default_context(X.device)
+    B, L = X.shape
+    if logits is None:
+        logits = torch.empty((B, NET_CLASSES), dtype=torch.float32, device=X.device)
+    _check(load_library().edm_net_forward_bf16(ctx.handle, _dev_ptr(params, torch.float32, "params"), C,
+                                               _dev_ptr(X, torch.float32, "X"), B, L, X.stride(0),
+                                               _dev_ptr(logits, torch.float32, "logits")), ctx.handle)
     return logits
 
 

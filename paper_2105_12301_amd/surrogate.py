@@ -53,11 +53,16 @@ class Surrogate:
                 log(f"epoch {ep}: loss {history[-1][0]:.4f} ({history[-1][1]:.2f} s)")
         return history
 
-    def logits(self, X, batch: int = 1024):
+    def logits(self, X, batch: int = 1024, bf16: bool | None = None):
+        """Inference logits; BF16 matrix-core convolutions when C allows it
+        (bf16=None), else float32 (training always runs in float32)."""
+        if bf16 is None:
+            bf16 = self.C in (32, 64)
+        fwd = edm.edm_net_forward_bf16 if bf16 else edm.edm_net_forward
         out = torch.empty((X.shape[0], edm.NET_CLASSES), dtype=torch.float32, device=X.device)
         for b0 in range(0, X.shape[0], batch):
             xb = X[b0:b0 + batch]
-            edm.edm_net_forward(self.params, self.C, xb, logits=out[b0:b0 + batch], ctx=self.ctx)
+            fwd(self.params, self.C, xb, logits=out[b0:b0 + batch], ctx=self.ctx)
         return out
 
     def select_E(self, X, E_max: int = 20, Tp: int = 1, m_top: int = 2, min_conf: float = 0.0,

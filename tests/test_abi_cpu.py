@@ -17,7 +17,7 @@ P = ctypes.c_void_p(256)  # a non-NULL stand-in; never dereferenced by validatio
 def declared_symbols():
     src = open(os.path.join(ROOT, "include", "edm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(edm_[A-Za-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(edm_[A-Za-z_0-9]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")

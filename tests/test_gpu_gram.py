@@ -1,0 +1,197 @@
+"""Matrix-core filtered scan (chosen form, E >= 9) against the oracle and the
+exact scans.
+
+The filter only decides which candidates are re-ranked exactly, so its tables
+must equal the oracle's bit for bit and every sweep / CCM result must equal
+the plain and batched forms bit for bit, on data that stresses the margin:
+exact duplicate windows (ties), long quiet stretches of calcium-like traces,
+a large constant offset, tiny and huge amplitudes (the latter switches the
+filter off), constant series, and lengths around the tile and block edges.
+"""
+import numpy as np
+import pytest
+
+from oracle import edm_oracle as O
+from paper_2105_12301_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RHO_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def edm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_12301_amd import edm as _edm
+
+    _edm.load_library()
+    return _edm
+
+
+@pytest.fixture(scope="module")
+def ctxs(edm):
+    cs = {name: edm.Context(device=0, form=f) for name, f in
+          (("plain", edm.EDM_FORM_PLAIN), ("batched", edm.EDM_FORM_BATCHED),
+           ("chosen", edm.EDM_FORM_CHOSEN))}
+    yield cs
+    for c in cs.values():
+        c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def logistic(L, s=0, seed=1):
+    X, _ = synth.coupled_logistic_pairs(seed=seed, n_pairs=4, L=L)
+    return X[s].copy()
+
+
+def calcium(L, s=0):
+    X = synth.calcium_like(seed=4, N=120, L=L)
+    X = X[0] if isinstance(X, tuple) else X
+    return np.ascontiguousarray(X[s], dtype=np.float32)
+
+
+def levels(L, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.integers(0, 3, size=L) * 0.5).astype(np.float32)
+
+
+KNN_CASES = [
+    # name, series, E, Tp
+    ("logistic E9", logistic(700, 0), 9, 1),
+    ("logistic E10 Tp0", logistic(700, 1), 10, 0),
+    ("logistic E11", logistic(700, 2), 11, 1),
+    ("logistic E12", logistic(700, 3), 12, 1),
+    ("logistic E13", logistic(700, 4), 13, 1),
+    ("logistic E14 Tp0", logistic(700, 5), 14, 0),
+    ("logistic E15", logistic(700, 6), 15, 1),
+    ("logistic E16", logistic(700, 7), 16, 1),
+    ("logistic E17", logistic(700, 0, 2), 17, 1),
+    ("logistic E18 Tp0", logistic(700, 1, 2), 18, 0),
+    ("logistic E19", logistic(700, 2, 2), 19, 1),
+    ("logistic E20", logistic(700, 3, 2), 20, 1),
+    ("calcium E9", calcium(900, 0), 9, 1),
+    ("calcium E14", calcium(900, 1), 14, 0),
+    ("calcium E20", calcium(900, 2), 20, 1),
+    ("tiled E9", synth.tiled_period(17 * 30, 17, 1), 9, 1),
+    ("tiled E16", synth.tiled_period(23 * 25, 23, 2), 16, 0),
+    ("tiled E20", synth.tiled_period(29 * 20, 29, 3), 20, 1),
+    ("ties E12", levels(400, 1), 12, 1),
+    ("ties E19", levels(300, 2), 19, 0),
+    ("offset E10", logistic(600, 4) + np.float32(1000.0), 10, 1),
+    ("offset E18", logistic(600, 5) + np.float32(1000.0), 18, 1),
+    ("tiny E11", logistic(500, 6) * np.float32(1e-20), 11, 1),
+    ("huge E13", logistic(500, 7) * np.float32(2e18), 13, 1),
+    ("constant E9", np.full(300, 0.37, np.float32), 9, 1),
+    ("ramp E15", synth.ramp(333), 15, 0),
+    ("nq=k+1 E9", logistic(19, 0), 9, 1),      # nq = 10, one candidate to spare
+    ("nq=32 E12", logistic(43, 1), 12, 0),
+    ("nq=33 E12", logistic(44, 1), 12, 0),
+    ("nq=256 E16", logistic(272, 2), 16, 1),
+    ("nq=257 E16", logistic(273, 2), 16, 1),
+    ("nq=513 E20", logistic(533, 3), 20, 1),
+]
+
+
+@pytest.mark.parametrize("case", KNN_CASES, ids=[c[0] for c in KNN_CASES])
+def test_filtered_knn_bit_exact(edm, ctxs, case):
+    _, x, E, Tp = case
+    idx, _, w = edm.edm_knn(dev(x), E, 1, Tp, want_dist=False, ctx=ctxs["chosen"])
+    ctxs["chosen"].sync()
+    oi, _ = O.knn(x, E, 1, Tp)
+    np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+    _, W = O.weights(x, oi, E, 1)
+    np.testing.assert_allclose(w.cpu().numpy(), W, rtol=0, atol=1e-6)
+
+
+def test_filtered_knn_long_series_sampled(edm, ctxs):
+    # Bench length (5000) and a long series (12000): sampled rows vs the oracle.
+    for L, E, seed in ((5000, 20, 0), (5000, 9, 3), (12000, 13, 1)):
+        X, _, _ = synth.logistic_network(seed=seed, N=4, L=L)
+        x = X[2]
+        idx, _, w = edm.edm_knn(dev(x), E, 1, 1, want_dist=False, ctx=ctxs["chosen"])
+        ctxs["chosen"].sync()
+        m = idx.shape[0]
+        rows = np.unique(np.r_[0, 1, 31, 32, 255, 256, m - 2, m - 1,
+                               np.random.default_rng(seed).integers(0, m, 30)])
+        oi, _ = O.knn_rows(x, E, 1, 1, rows)
+        np.testing.assert_array_equal(idx.cpu().numpy()[rows], oi)
+
+
+def _sweep_all(edm, ctxs, X, lens, E_max):
+    out = {}
+    for name, c in ctxs.items():
+        r, e = edm.edm_simplex_sweep(dev(X), lengths=lens, E_max=E_max, ctx=c)
+        c.sync()
+        out[name] = (r, e)
+    return out
+
+
+@pytest.mark.parametrize("family", ["logistic", "calcium", "mixed"])
+def test_filtered_sweep_bit_identical(edm, ctxs, family):
+    if family == "logistic":
+        X, _, _ = synth.logistic_network(seed=5, N=12, L=1500)
+        lens = np.full(12, 1500)
+        lens[[2, 7]] = [700, 29]
+    elif family == "calcium":
+        X = synth.calcium_like(seed=4, N=120, L=1200)
+        X = np.ascontiguousarray((X[0] if isinstance(X, tuple) else X)[:10], dtype=np.float32)
+        lens = np.full(10, 1200)
+    else:
+        X, _, _ = synth.logistic_network(seed=6, N=8, L=900)
+        X[1] = synth.tiled_period(900, 31, 4)
+        X[2] = X[2] + np.float32(500.0)
+        X[3] = X[3] * np.float32(2e18)
+        X[4] = np.float32(0.25)
+        X[5] = levels(900, 7)
+        lens = np.full(8, 900)
+        lens[6] = 40
+    res = _sweep_all(edm, ctxs, X, lens, 20)
+    rp, ep = res["plain"]
+    for name in ("batched", "chosen"):
+        r, e = res[name]
+        assert torch.equal(rp.view(torch.int32), r.view(torch.int32)), name
+        assert torch.equal(ep, e), name
+    sel = [0, 2] if family != "mixed" else [1, 2, 5]
+    ro, _ = O.simplex_sweep(X[sel], lens[sel], 20)
+    g = res["chosen"][0].cpu().numpy()[sel]
+    assert np.array_equal(np.isnan(g), np.isnan(ro))
+    assert np.nanmax(np.abs(g - ro)) <= RHO_TOL
+
+
+@pytest.mark.parametrize("E_max", [9, 12, 14, 17])
+def test_filtered_sweep_partial_groups(edm, ctxs, E_max):
+    # E_max inside a group: the filtered groups are cut at E_max.
+    X, _, _ = synth.logistic_network(seed=7, N=6, L=800)
+    lens = np.full(6, 800)
+    res = _sweep_all(edm, ctxs, X, lens, E_max)
+    rp, ep = res["plain"]
+    rc, ec = res["chosen"]
+    assert torch.equal(rp.view(torch.int32), rc.view(torch.int32))
+    assert torch.equal(ep, ec)
+
+
+@pytest.mark.parametrize("limit", [None, 4 << 20])
+def test_filtered_ccm_bit_identical(edm, ctxs, limit, monkeypatch):
+    # Targets whose E covers every filtered group; a small workspace limit
+    # splits the libraries into several batches.
+    if limit:
+        monkeypatch.setenv("EDM_WORKSPACE_LIMIT", str(limit))
+    X, lens, _ = synth.spike_trains(seed=11, N=30, L_min=300, L_max=1100)
+    E = (np.arange(30) % 12 + 9).astype(np.int32)
+    E[[0, 5]] = [2, 7]
+    Xd, Ed = dev(X), dev(E)
+    out = {}
+    for name, c in ctxs.items():
+        out[name] = edm.edm_ccm(Xd, Ed, Lx=lens, Ly=lens, ctx=c)
+        c.sync()
+    for name in ("batched", "chosen"):
+        assert torch.equal(out["plain"].view(torch.int32), out[name].view(torch.int32)), name
+    ro = O.ccm(X, lens, X, lens, E, lib_rows=[3, 21])
+    g = out["chosen"].cpu().numpy()[[3, 21]]
+    assert np.array_equal(np.isnan(g), np.isnan(ro))
+    assert np.nanmax(np.abs(g - ro)) <= RHO_TOL

@@ -50,6 +50,30 @@ def test_forward_logits(edm, ctx, C, L, B):
     np.testing.assert_allclose(lg.cpu().numpy(), ref, rtol=1e-4, atol=1e-5)
 
 
+@pytest.mark.parametrize("C,L,B", [(64, 300, 3), (64, 1500, 2), (32, 257, 3), (64, 5, 2)])
+def test_forward_bf16_logits(edm, ctx, C, L, B):
+    # BF16 inference form against the oracle's emulation of it (weights and
+    # C->C inputs rounded to BF16, exact products, float64 sums).  The GPU sums
+    # in FP32 and rounds its own FP32 activations, so a value sitting on a
+    # BF16 rounding boundary may round the other way: the bar is 1e-3 of the
+    # logit scale, against ~1e-2 for the BF16-vs-float64 difference itself.
+    theta, X, _ = case(C, L, B, 3 * C + L)
+    lg = edm.edm_net_forward_bf16(dev(theta), C, dev(X), ctx=ctx)
+    ctx.sync()
+    got = lg.cpu().numpy()
+    emu = NO.forward_bf16(theta.astype(np.float64), X, C)
+    ref, _ = NO.forward(theta.astype(np.float64), X, C)
+    scale = max(1.0, float(np.abs(ref).max()))
+    assert np.abs(got - emu).max() <= 1e-3 * scale
+    assert np.abs(got - ref).max() <= 3e-2 * scale
+
+
+def test_forward_bf16_rejects_other_widths(edm, ctx):
+    theta, X, _ = case(16, 64, 2, 1)
+    with pytest.raises(edm.EdmError):
+        edm.edm_net_forward_bf16(dev(theta), 16, dev(X), ctx=ctx)
+
+
 @pytest.mark.parametrize("C,L,B", [(8, 64, 5), (8, 200, 4), (64, 300, 3)])
 def test_loss_and_gradients(edm, ctx, C, L, B):
     theta, X, y = case(C, L, B, 7 * C + L)

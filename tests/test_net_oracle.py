@@ -63,3 +63,30 @@ def test_first_adam_step_moves_by_lr_times_sign():
     g = rng.normal(size=50)
     new, m, v = N.adam_step(th, g, np.zeros(50), np.zeros(50), 1, 1e-3, eps=0.0)
     np.testing.assert_allclose(new, th - 1e-3 * np.sign(g), rtol=0, atol=1e-15)
+
+
+def test_bf16_round_known_values():
+    # BF16 keeps 8 significant bits: 1 + 2^-8 is a tie between 1 and 1 + 2^-7
+    # (ties to even -> 1), 1 + 3*2^-9 rounds up, negative values mirror, and
+    # a value that is already BF16 is unchanged.
+    x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -9, 1.0 + 2.0 ** -7 + 2.0 ** -8,
+                  -(1.0 + 3 * 2.0 ** -9), 3.140625, 0.0, 2.0 ** -130])
+    want = np.array([1.0, 1.0, 1.0 + 2.0 ** -7, 1.0 + 2.0 ** -6,
+                     -(1.0 + 2.0 ** -7), 3.140625, 0.0, 2.0 ** -130])
+    np.testing.assert_array_equal(N.bf16_round(x), want)
+    r = np.random.default_rng(0).normal(size=1000)
+    rel = np.abs(N.bf16_round(r) - r) / np.abs(r)
+    assert rel.max() <= 2.0 ** -8
+
+
+def test_bf16_forward_close_to_float64():
+    # The BF16 inference form moves logits only by the rounding of weights
+    # and activations (relative 2^-8 each, partly averaging out over time).
+    rng = np.random.default_rng(1)
+    C, L, B = 8, 64, 4
+    theta = rng.normal(scale=0.3, size=N.param_count(C))
+    X = rng.normal(size=(B, L))
+    ref, _ = N.forward(theta, X, C)
+    got = N.forward_bf16(theta, X, C)
+    assert np.max(np.abs(got - ref)) <= 0.02 * np.max(np.abs(ref))
+    assert np.max(np.abs(got - ref)) > 0.0
