@@ -46,9 +46,16 @@
 // * K-slots of the contraction: lags 0..E_hi-1, then one norm slot per E of
 //   the group, then zeros.  A group fits one 16-slot chunk (E_hi + |group| <=
 //   16), or for E >= 16 a shared chunk of lags 0..15 plus one chunk per E.
-// * Survivors of a tile: the lanes walk their bits under a wave-uniform loop;
-//   the exact key of a survivor costs E_hi LDS reads and 3 E_hi VALU ops.
+// * Two passes over the candidate tiles.  Pass 1 keeps, per lane and value
+//   slot, the candidate with the smallest estimate at E_hi (one hi*hi product
+//   per chunk suffices to rank them); the exact keys
+//   of a query's 32 slot winners give an upper bound of its final k-th key
+//   for every E of the group before any list exists.  Pass 2 filters against
+//   min(bound, current k-th key) and queues the survivors per lane in LDS;
+//   a queue is re-ranked (exact key: E_hi LDS reads and 3 E_hi VALU ops, then
+//   the sorted insertions) only when some lane's queue fills, and at the end.
 #include <cstdint>
+#include <type_traits>
 
 #include "../../include/edm.h"
 #include "device_common.h"
@@ -70,6 +77,7 @@ static_assert(kGramWaves * 32 == kKnnThreads, "a workgroup covers one query bloc
 constexpr float kGramScale = 1.0f - 0x1p-12f;  // s = 1 - 2^-12
 constexpr float kGramFloor = 0x1p-90f;          // absolute slack: flushed tiny products
 constexpr float kGramSafeMax = 0x1p56f;         // larger |x - mu| switches the filter off
+constexpr int kQueueCap = 32;                   // queued survivors per lane before a re-rank
 
 __device__ __forceinline__ uint32_t bf16_bits(float f) {  // round to nearest even (finite f)
   const uint32_t u = __float_as_uint(f);
@@ -100,6 +108,31 @@ __device__ __forceinline__ void read_window(const uint32_t *__restrict__ w32, in
   for (int i = 0; i < 5; ++i) W[i] = w32[w0 + i];
 #pragma unroll
   for (int i = 0; i < 4; ++i) out[i] = __builtin_amdgcn_alignbit(W[i + 1], W[i], sh);
+}
+
+// Ascending bitonic sort of 32 values held in registers.
+__device__ __forceinline__ void sort32(float (&a)[32]) {
+#pragma unroll
+  for (int k = 2; k <= 32; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int i = 0; i < 32; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const float x = a[i], y = a[l];
+          const bool up = (i & k) == 0;
+          a[i] = up ? fminf(x, y) : fmaxf(x, y);
+          a[l] = up ? fmaxf(x, y) : fminf(x, y);
+        }
+      }
+}
+
+// Largest value of v over the wave (butterfly over the 64 lanes).
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int m = 1; m < kWave; m <<= 1) v = max(v, __shfl_xor(v, m));
+  return __builtin_amdgcn_readfirstlane(v);
 }
 
 __device__ __forceinline__ f32x16_t mfma(const uint32_t (&a)[4], const uint32_t (&b)[4],
@@ -237,6 +270,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   uint16_t *xl = xh + ld;
   const uint32_t *xh32 = reinterpret_cast<const uint32_t *>(xh);
   const uint32_t *xl32 = reinterpret_cast<const uint32_t *>(xl);
+  uint16_t *qbuf_all = xl + ld;  // [wave][kQueueCap][64] survivor queues
   const float mu = a.gram_mu[row];
   const uint32_t *__restrict__ nrm =
       a.gram_nrm + (static_cast<int64_t>(row) * kGramNE + (ELO - kGramEMin)) * ld;
@@ -288,15 +322,6 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   float nq[NG], thr[NG];
 #pragma unroll
   for (int g = 0; g < NG; ++g) nq[g] = unpack_sum(nrm[g * ld + pc]);
-  auto refresh = [&]() {
-    static_for<ELO, EHI>([&](auto EC) {
-      constexpr int E = decltype(EC)::value;
-      const float kth = qk[list_off<ELO>(E) + E];
-      thr[E - ELO] = kth < 0.0f ? -__builtin_inff()
-                                : (unsafe ? __builtin_inff() : (kth - nq[E - ELO]) + kGramFloor);
-    });
-  };
-  refresh();
 
   // Query operands (fixed for the scan).
   uint32_t bsh[4], bsl[4];
@@ -325,39 +350,172 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     }
   });
 
-  if (pw < m_lo) {
-#pragma unroll 1
-    for (int c0 = 0; c0 < m_lo; c0 += 32) {
-      const int qa = c0 + n;  // candidate of the A rows this lane supplies
-      uint32_t nr[NG];
+  // Candidate operands of the tile starting at c0 (A rows: candidates
+  // c0 .. c0+31) and the shared chunk's partial products.
+  // The candidate norms come from global memory: they are loaded one tile
+  // ahead (fetch) so the load latency overlaps the current tile's work.
+  uint32_t ah[NCH][4], al[NCH][4];
+  f32x16_t acc_s = {};
+  uint32_t nr[NG], nr_next[NG];
+  auto fetch = [&](int c0) {
 #pragma unroll
-      for (int g = 0; g < NG; ++g) nr[g] = nrm[g * ld + qa];
-      uint32_t ah[NCH][4], al[NCH][4];
-      static_for<0, NCH - 1>([&](auto CC) {
-        constexpr int C = decltype(CC)::value;
-        uint32_t wh[4], wl[4];
-        read_window(xh32, qa + 16 * C + (h1 ? 8 : 0), wh);
-        read_window(xl32, qa + 16 * C + (h1 ? 8 : 0), wl);
-        build_a<Lay, C>(ah[C], al[C], wh, wl, nr, h1);
-      });
-      f32x16_t acc_s = {};
-      if constexpr (Lay::kShared) {
-        acc_s = mfma(ah[0], bsh, acc_s);
+    for (int g = 0; g < NG; ++g) nr_next[g] = nrm[g * ld + c0 + n];
+  };
+  // HI_ONLY (pass 1) builds just the hi operands and the hi*hi product.
+  auto load_tile = [&](int c0, auto hi_only) {
+    constexpr bool HI_ONLY = decltype(hi_only)::value;
+    const int qa = c0 + n;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) nr[g] = nr_next[g];
+    fetch(c0 + 32);  // in bounds: the norm rows hold gram_ld >= L + 64 entries
+    static_for<0, NCH - 1>([&](auto CC) {
+      constexpr int C = decltype(CC)::value;
+      uint32_t wh[4], wl[4] = {0u, 0u, 0u, 0u};
+      read_window(xh32, qa + 16 * C + (h1 ? 8 : 0), wh);
+      if constexpr (!HI_ONLY) read_window(xl32, qa + 16 * C + (h1 ? 8 : 0), wl);
+      build_a<Lay, C>(ah[C], al[C], wh, wl, nr, h1);
+    });
+    acc_s = f32x16_t{};
+    if constexpr (Lay::kShared) {
+      acc_s = mfma(ah[0], bsh, acc_s);
+      if constexpr (!HI_ONLY) {
         acc_s = mfma(ah[0], bsl, acc_s);
         acc_s = mfma(al[0], bsh, acc_s);
       }
+    }
+  };
+  auto estimate = [&](int g) {
+    f32x16_t acc = acc_s;
+#pragma unroll
+    for (int C = C0; C < NCH; ++C) {
+      acc = mfma(ah[C], bh[g][C - C0], acc);
+      acc = mfma(ah[C], bl[g][C - C0], acc);
+      acc = mfma(al[C], bh[g][C - C0], acc);
+    }
+    return acc;
+  };
+  // Pass-1 estimate at E_hi from the hi halves only (one product per chunk):
+  // it only ranks candidates; the bound it leads to uses exact keys.
+  auto estimate_hi = [&]() {
+    f32x16_t acc = acc_s;
+#pragma unroll
+    for (int C = C0; C < NCH; ++C) acc = mfma(ah[C], bh[NG - 1][C - C0], acc);
+    return acc;
+  };
+  // Exact float32 keys of candidate q for every E of the group (Algorithm 1,
+  // one running sum); +inf where q is not a candidate of that E.
+  auto exact_keys = [&](int q, bool ok, float (&key)[NG]) {
+    float acc = 0.0f;
+    static_for<0, EHI - 1>([&](auto JC) {
+      constexpr int j = decltype(JC)::value;
+      const float d = vp[j] - xs[q + j];
+      acc = acc + d * d;
+      if constexpr (j + 1 >= ELO) {
+        constexpr int E = j + 1;
+        key[E - ELO] = (ok && q < L - (E - 1) - Tp) ? acc : __builtin_inff();
+      }
+    });
+  };
+
+  // Pass 1 (estimates only): lane v-slot b keeps the candidate with the
+  // smallest estimate at E_hi among candidates 32t + m(b); the 32 winners of
+  // a query (16 per lane) are distinct candidates, so the K-th smallest of
+  // their exact keys bounds the query's final K-th key from above, for every
+  // E of the group.  These bounds cap the thresholds of pass 2 from the start.
+  float ub[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) ub[g] = __builtin_inff();
+  if (pw < m_lo) {
+    float bm[16];
+    int bt[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      bm[v] = __builtin_inff();
+      bt[v] = -1;
+    }
+    fetch(0);
+#pragma unroll 1
+    for (int c0 = 0; c0 < m_lo; c0 += 32) {
+      load_tile(c0, std::true_type{});
+      const f32x16_t acc = estimate_hi();
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const bool lt = acc[v] < bm[v];
+        bm[v] = lt ? acc[v] : bm[v];
+        bt[v] = lt ? c0 : bt[v];
+      }
+    }
+    float kb[NG][16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int q = bt[v] + 8 * (v >> 2) + (h1 ? 4 : 0) + (v & 3);
+      float key[NG];
+      exact_keys(bt[v] < 0 ? 0 : q, bt[v] >= 0 && q != p, key);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) kb[g][v] = key[g];
+    }
+    static_for<ELO, EHI>([&](auto EC) {
+      constexpr int E = decltype(EC)::value;
+      float a[32];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        a[v] = kb[E - ELO][v];
+        a[16 + v] = __shfl_xor(kb[E - ELO][v], 32);
+      }
+      sort32(a);
+      ub[E - ELO] = a[E];  // K-th smallest, K = E + 1
+    });
+  }
+
+  // Pass 2: survivors of each tile (estimate within the margin of the
+  // threshold for some E) are queued per lane in LDS in ascending candidate
+  // order and re-ranked in batches, so the lists change only at a flush.
+  uint16_t *qbuf = qbuf_all + wave * (kQueueCap * kWave) + lane;  // entry i at qbuf[i * 64]
+  int cnt = 0;
+  auto refresh = [&]() {
+    static_for<ELO, EHI>([&](auto EC) {
+      constexpr int E = decltype(EC)::value;
+      const float own = qk[list_off<ELO>(E) + E];
+      const float kth = fminf(fminf(own, __shfl_xor(own, 32)), ub[E - ELO]);
+      thr[E - ELO] = own < 0.0f ? -__builtin_inff()
+                                : (unsafe ? __builtin_inff() : (kth - nq[E - ELO]) + kGramFloor);
+    });
+  };
+  // Re-rank the queued candidates: uniform trip count and a branch-free body
+  // keep the lists in place in registers.
+  auto flush = [&]() {
+    const int n_iter = wave_max(cnt);
+#pragma unroll 1
+    for (int it = 0; it < n_iter; ++it) {
+      const bool has = it < cnt;
+      const int q = has ? static_cast<int>(qbuf[it * kWave]) : 0;
+      float key[NG];
+      exact_keys(q, has && q != p, key);
+      static_for<ELO, EHI>([&](auto EC) {
+        constexpr int E = decltype(EC)::value;
+        // The empty asm hides the +inf of idle lanes from the optimiser,
+        // which would otherwise branch around the insertion.
+        float kin = key[E - ELO];
+        asm volatile("" : "+v"(kin));
+        if (__builtin_amdgcn_ballot_w64(kin < qk[list_off<ELO>(E) + E]))
+          slice_insert<list_off<ELO>(E), E + 1, TOT>(qk, qi, kin, q);
+      });
+    }
+    cnt = 0;
+    refresh();
+  };
+  refresh();
+  if (pw < m_lo) {
+    fetch(0);
+#pragma unroll 1
+    for (int c0 = 0; c0 < m_lo; c0 += 32) {
+      load_tile(c0, std::false_type{});
       bool surv[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) surv[v] = false;
-      static_for<ELO, EHI>([&](auto EC) {
-        constexpr int g = decltype(EC)::value - ELO;
-        f32x16_t acc = acc_s;
-#pragma unroll
-        for (int C = C0; C < NCH; ++C) {
-          acc = mfma(ah[C], bh[g][C - C0], acc);
-          acc = mfma(ah[C], bl[g][C - C0], acc);
-          acc = mfma(al[C], bh[g][C - C0], acc);
-        }
+      static_for<0, NG - 1>([&](auto GC) {
+        constexpr int g = decltype(GC)::value;
+        const f32x16_t acc = estimate(g);
 #pragma unroll
         for (int v = 0; v < 16; ++v) surv[v] = surv[v] || !(acc[v] > thr[g]);
       });
@@ -368,31 +526,17 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
         uint32_t bits = 0;
 #pragma unroll
         for (int v = 0; v < 16; ++v) bits |= surv[v] ? (1u << v) : 0u;
-#pragma unroll 1
-        while (__builtin_amdgcn_ballot_w64(bits != 0u)) {
-          const bool has = bits != 0u;
-          const int v = has ? __builtin_ctz(bits) : 0;
+        if (__builtin_amdgcn_ballot_w64(cnt + __builtin_popcount(bits) > kQueueCap)) flush();
+        while (bits) {
+          const int v = __builtin_ctz(bits);
           bits &= bits - 1u;
-          const int q = c0 + 8 * (v >> 2) + (h1 ? 4 : 0) + (v & 3);
-          const bool ok = has && q != p;
-          float acc = 0.0f;
-          float key[NG];
-          static_for<0, EHI - 1>([&](auto JC) {
-            constexpr int j = decltype(JC)::value;
-            const float d = vp[j] - xs[q + j];
-            acc = acc + d * d;
-            if constexpr (j + 1 >= ELO) key[j + 1 - ELO] = acc;
-          });
-          static_for<ELO, EHI>([&](auto EC) {
-            constexpr int E = decltype(EC)::value;
-            slice_offer<list_off<ELO>(E), E + 1, TOT>(qk, qi, key[E - ELO], q,
-                                                      ok && q < L - (E - 1) - Tp);
-          });
+          qbuf[cnt * kWave] = static_cast<uint16_t>(c0 + 8 * (v >> 2) + (h1 ? 4 : 0) + (v & 3));
+          ++cnt;
         }
-        refresh();
       }
     }
   }
+  flush();
 
   // Each query's two half-lists -> its full list (both lanes end equal).
   static_for<ELO, EHI>([&](auto EC) {
@@ -536,7 +680,8 @@ hipError_t launch_gram_group(const KnnArgs &a, int lo, int hi, int nslots, int64
   const GramFn fn = pick(lo, hi);
   if (fn == nullptr || L_max > kGramLMax || a.gram_ld < L_max + kGramPad || a.tau != 1)
     return hipErrorInvalidValue;
-  const size_t shm = static_cast<size_t>(a.gram_ld) * (sizeof(float) + 2 * sizeof(uint16_t));
+  const size_t shm = static_cast<size_t>(a.gram_ld) * (sizeof(float) + 2 * sizeof(uint16_t)) +
+                     sizeof(uint16_t) * kQueueCap * kGramThreads;
   const void *f = reinterpret_cast<const void *>(fn);
   if (shm > 65536) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,

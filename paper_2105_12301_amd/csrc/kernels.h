@@ -85,7 +85,7 @@ hipError_t launch_tables_persistent(const KnnArgs &a, int group, const TableItem
 constexpr int kGramEMin = 9;
 constexpr int kGramNE = EDM_E_MAX - kGramEMin + 1;
 constexpr int kGramPad = 64;  // zero samples staged past the end of a series
-constexpr int64_t kGramLMax = 16384;
+constexpr int64_t kGramLMax = 14336;
 inline int64_t gram_ld(int64_t L_max) { return (L_max + kGramPad + 63) / 64 * 64; }
 // Per slot: centring constant, then the packed norms of every E >= kGramEMin.
 hipError_t launch_gram_prep(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t st);

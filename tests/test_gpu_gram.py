@@ -88,7 +88,7 @@ KNN_CASES = [
     ("huge E13", logistic(500, 7) * np.float32(2e18), 13, 1),
     ("constant E9", np.full(300, 0.37, np.float32), 9, 1),
     ("ramp E15", synth.ramp(333), 15, 0),
-    ("nq=k+1 E9", logistic(19, 0), 9, 1),      # nq = 10, one candidate to spare
+    ("nq=k+1 E9", logistic(20, 0), 9, 1),      # nq = 11: exactly k candidates besides self
     ("nq=32 E12", logistic(43, 1), 12, 0),
     ("nq=33 E12", logistic(44, 1), 12, 0),
     ("nq=256 E16", logistic(272, 2), 16, 1),
