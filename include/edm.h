@@ -166,6 +166,24 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl,
             int64_t ldy, const int32_t *E_tgt, int32_t tau, int32_t Tp,
             float *rho);
 
+/* The method's pipeline in one call (Section 3.4): the simplex E sweep of
+ * every series (Tp = 1, E = 1..E_max) picks each series' E*, then every
+ * ordered pair is cross-mapped at the target's E* (Tp = 0), the series being
+ * both the libraries and the targets.  Results equal edm_simplex_sweep
+ * followed by edm_ccm with E_tgt = E_opt and Tp = 0.
+ * In EDM_FORM_CHOSEN with tau = 1 (and the sweep's lists of every E fitting
+ * the workspace limit) the cross map's tables are derived from the sweep's:
+ * at dimension E the Tp = 0 candidates are the Tp = 1 candidates plus the
+ * point m1 = L - E, so a query's table is its sweep list with that point
+ * offered last, and only query m1 needs a scan.  One stream sync (E_opt is
+ * read back to group the targets).
+ * X       : float32 [N][ldx] series, lengths L (host) [N]
+ * rho_sweep, E_opt : as edm_simplex_sweep
+ * rho     : float32 [N][N], rho[i][j] = library i, target j; NaN where the
+ *           pair is undefined (L[j] < L[i], E_opt[j] = 0, a constant side). */
+int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int64_t ldx,
+                  int32_t E_max, int32_t tau, float *rho_sweep, int32_t *E_opt, float *rho);
+
 /* ---------------------------------------------------------------------------
  * Batched CCM plan: libraries of uneven length and targets of uneven E in
  * one graph of persistent launches (Section 3.4's grouping by E, batched over

@@ -346,6 +346,139 @@ int edm_simplex_sweep(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N,
   return EDM_OK;
 }
 
+int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int64_t ldx,
+                  int32_t E_max, int32_t tau, float *rho_sweep, int32_t *E_opt, float *rho) {
+  std::string msg;
+  const int rc = edm::check_sweep(X, L, N, ldx, E_max, tau, 1, rho_sweep, E_opt, msg);
+  if (rc != EDM_OK) return set_err(ctx, rc, msg);
+  if (N > 0 && !rho) return set_err(ctx, EDM_E_ARG, "NULL rho");
+  EDM_RC(check_ctx(ctx));
+  if (N == 0) return EDM_OK;
+  if (N > INT32_MAX) return set_err(ctx, EDM_E_ARG, "too many series");
+  const int64_t L_max = *std::max_element(L, L + N);
+
+  // Workspace of the fused form: the sweep's lists of every E, and one E's
+  // cross-map tables at a time.
+  const int32_t mom_blocks = static_cast<int32_t>((L_max + edm::kKnnThreads - 1) / edm::kKnnThreads);
+  const bool gram = E_max >= edm::kGramEMin && L_max <= edm::kGramLMax;
+  const int64_t g_ld = edm::gram_ld(L_max);
+  Plan plan;
+  const size_t off_L = plan.take(sizeof(int64_t) * N);
+  const size_t off_ids = plan.take(sizeof(int32_t) * N);
+  const size_t off_mom = plan.take(edm::kMomBytes * static_cast<size_t>(N) * E_max * mom_blocks);
+  size_t off_gmu = 0, off_gnrm = 0;
+  if (gram) {
+    off_gmu = plan.take(sizeof(float) * N);
+    off_gnrm = plan.take(sizeof(uint32_t) * static_cast<size_t>(edm::kGramNE) * g_ld * N);
+  }
+  std::vector<size_t> off_keep(EDM_E_MAX + 1, 0);
+  std::vector<int64_t> keep_stride(EDM_E_MAX + 1, 0);
+  size_t tbl_bytes = 0;
+  for (int E = 1; E <= E_max; ++E) {
+    const int64_t m1 = L_max - E;  // sweep queries at E (Tp = 1)
+    if (m1 > 0) {
+      keep_stride[E] = m1 * (E + 1);
+      off_keep[E] = plan.take(sizeof(int32_t) * static_cast<size_t>(keep_stride[E]) * N);
+    }
+    tbl_bytes = std::max(tbl_bytes, static_cast<size_t>(m1 + 1) * (E + 1) * 8 * static_cast<size_t>(N));
+  }
+  const size_t off_tbl = plan.take(tbl_bytes);
+  const bool fused = (ctx->form == EDM_FORM_CHOSEN) && tau == 1 && plan.bytes <= workspace_limit();
+  if (!fused) {  // the sweep, then the cross map at the selected E (Tp = 0)
+    EDM_RC(edm_simplex_sweep(ctx, X, L, N, ldx, E_max, tau, 1, rho_sweep, E_opt));
+    return edm_ccm(ctx, X, L, N, ldx, X, L, N, ldx, E_opt, tau, 0, rho);
+  }
+  EDM_RC(ws_reserve(ctx, plan.bytes));
+  int64_t *L_dev = reinterpret_cast<int64_t *>(ctx->ws + off_L);
+  int32_t *ids_dev = reinterpret_cast<int32_t *>(ctx->ws + off_ids);
+  edm::Mom *mom = reinterpret_cast<edm::Mom *>(ctx->ws + off_mom);
+  EDM_RC(upload(ctx, L, sizeof(int64_t) * N, L_dev));
+
+  edm::KnnArgs a{};
+  a.X = X;
+  a.ldx = ldx;
+  a.L_dev = L_dev;
+  a.Tp = 1;
+  a.tau = 1;
+  a.mom = mom;
+  a.mom_blocks = mom_blocks;
+  a.E_max = E_max;
+  a.status = ctx->status;
+  for (int E = 1; E <= E_max; ++E) {
+    if (keep_stride[E] == 0) continue;
+    a.keepE[E] = reinterpret_cast<int32_t *>(ctx->ws + off_keep[E]);
+    a.keep_strideE[E] = keep_stride[E];
+  }
+  if (gram) {
+    a.gram_mu = reinterpret_cast<float *>(ctx->ws + off_gmu);
+    a.gram_nrm = reinterpret_cast<uint32_t *>(ctx->ws + off_gnrm);
+    a.gram_ld = g_ld;
+    EDM_HIP(ctx, edm::launch_gram_prep(a, static_cast<int>(N), L_max, ctx->stream));
+  }
+  EDM_HIP(ctx, edm::launch_sweep_multi(a, static_cast<int>(N), L_max, ctx->stream));
+  EDM_HIP(ctx, edm::launch_sweep_finalize(mom, mom_blocks, L_dev, N, E_max, 1, 1, nullptr, rho_sweep,
+                                          E_opt, ctx->stream));
+
+  // Targets by their selected E (Section 3.4).
+  std::vector<int32_t> Eh(static_cast<size_t>(N));
+  EDM_HIP(ctx, hipMemcpyAsync(Eh.data(), E_opt, sizeof(int32_t) * N, hipMemcpyDeviceToHost, ctx->stream));
+  EDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  std::vector<std::vector<int32_t>> bucket(EDM_E_MAX + 1);
+  for (int64_t j = 0; j < N; ++j) {
+    const int e = Eh[static_cast<size_t>(j)];
+    if (e >= 1 && e <= E_max) bucket[e].push_back(static_cast<int32_t>(j));
+  }
+  std::vector<int32_t> ids;
+  std::vector<int64_t> at(EDM_E_MAX + 1, 0);
+  for (int e = 1; e <= EDM_E_MAX; ++e) {
+    at[e] = static_cast<int64_t>(ids.size());
+    ids.insert(ids.end(), bucket[e].begin(), bucket[e].end());
+  }
+  if (!ids.empty()) EDM_RC(upload(ctx, ids.data(), sizeof(int32_t) * ids.size(), ids_dev));
+  EDM_HIP(ctx, edm::launch_fill(rho, N * N, __builtin_nanf(""), ctx->stream));
+
+  for (int e = 1; e <= E_max; ++e) {
+    if (bucket[e].empty()) continue;
+    const int64_t m0 = L_max - (e - 1);  // cross-map queries at e (Tp = 0)
+    if (m0 - 1 < e + 1) continue;        // no library is long enough for this E
+    edm::KnnArgs t{};
+    t.X = X;
+    t.ldx = ldx;
+    t.L_dev = L_dev;
+    t.tau = 1;
+    t.Tp = 0;
+    t.E_max = EDM_E_MAX;
+    t.status = ctx->status;
+    t.need = 1u << (e - 1);
+    t.keepE[e] = a.keepE[e];
+    t.keep_strideE[e] = a.keep_strideE[e];
+    const int64_t stride = m0 * (e + 1);
+    t.idxE[e] = reinterpret_cast<int32_t *>(ctx->ws + off_tbl);
+    t.wE[e] = reinterpret_cast<float *>(ctx->ws + off_tbl + sizeof(int32_t) * stride * N);
+    t.strideE[e] = stride;
+    EDM_HIP(ctx, edm::launch_tables_from_sweep(t, e, static_cast<int>(N), L_max, ctx->stream));
+    edm::LookupArgs b{};
+    b.idx = t.idxE[e];
+    b.w = t.wE[e];
+    b.tbl_stride = stride;
+    b.Lx_dev = L_dev;
+    b.E = e;
+    b.tau = 1;
+    b.Tp = 0;
+    b.k = e + 1;
+    b.Y = X;
+    b.ldy = ldx;
+    b.Ly_dev = L_dev;
+    b.tgt_ids = ids_dev + at[e];
+    b.ntgt = static_cast<int32_t>(bucket[e].size());
+    b.rho = rho;
+    b.ldrho = N;
+    b.status = ctx->status;
+    EDM_HIP(ctx, edm::launch_lookup(b, static_cast<int>(N), m0, ctx->stream));
+  }
+  return EDM_OK;
+}
+
 int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t ldx,
             const float *Y, const int64_t *Ly, int64_t Nt, int64_t ldy, const int32_t *E_tgt,
             int32_t tau, int32_t Tp, float *rho) {

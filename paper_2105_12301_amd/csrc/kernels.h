@@ -52,6 +52,11 @@ struct KnnArgs {
   float *gram_mu;
   uint32_t *gram_nrm;
   int64_t gram_ld;
+  // Sweep mode: when keepE[E] is set, the sorted neighbour list of every
+  // query at E is also written there ([slot][m][E+1] int32, slot stride
+  // keep_strideE[E]) for a later cross map (launch_tables_from_sweep).
+  int32_t *keepE[EDM_E_MAX + 1];
+  int64_t keep_strideE[EDM_E_MAX + 1];
 };
 
 // Work item of the persistent table kernel: E group and query block of a row.
@@ -93,6 +98,12 @@ hipError_t launch_gram_prep(const KnnArgs &a, int nslots, int64_t L_max, hipStre
 // same outputs as launch_sweep_multi.
 hipError_t launch_gram_group(const KnnArgs &a, int lo, int hi, int nslots, int64_t L_max,
                              hipStream_t st);
+
+// Cross-map tables (Tp = 0) of dimension E for `nslots` libraries from the
+// sweep's lists (Tp = 1) in a.keepE[E]; output in a.idxE[E] / a.wE[E] with
+// a.strideE[E], as the batched table mode writes them.
+hipError_t launch_tables_from_sweep(const KnnArgs &a, int E, int nslots, int64_t L_max,
+                                    hipStream_t st);
 
 // Launch the kNN kernel for `nslots` libraries whose longest series has
 // `L_max` samples.  Returns a hipError_t.

@@ -41,7 +41,7 @@ NET_C_MAX = 64
 EXPORTS = (
     "edm_ctx_create", "edm_ctx_set_form", "edm_sync", "edm_last_error",
     "edm_ctx_destroy", "edm_embed", "edm_knn", "edm_lookup",
-    "edm_simplex_sweep", "edm_ccm",
+    "edm_simplex_sweep", "edm_ccm", "edm_sweep_ccm",
     "edm_net_param_count", "edm_net_forward", "edm_net_forward_bf16", "edm_net_loss_grad",
     "edm_net_adam",
     "edm_select_E",
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         lib.edm_lookup.argtypes = [_p, _p, _p, _i64, _i32, _i32, _i32, _i32, _p, _i64, _i64, _p, _p]
         lib.edm_simplex_sweep.argtypes = [_p, _p, _p, _i64, _i64, _i32, _i32, _i32, _p, _p]
         lib.edm_ccm.argtypes = [_p, _p, _p, _i64, _i64, _p, _p, _i64, _i64, _p, _i32, _i32, _p]
+        lib.edm_sweep_ccm.argtypes = [_p, _p, _p, _i64, _i64, _i32, _i32, _p, _p, _p]
         lib.edm_net_param_count.argtypes = [_i32]
         lib.edm_net_param_count.restype = _i64
         lib.edm_net_forward.argtypes = [_p, _p, _i32, _p, _i64, _i64, _i64, _p]
@@ -286,6 +287,24 @@ def edm_ccm(X, E_tgt, Y=None, Lx=None, Ly=None, tau: int = 1, Tp: int = 0, rho=N
         _dev_ptr(E_tgt, torch.int32, "E_tgt"), tau, Tp, _dev_ptr(rho, torch.float32, "rho")),
         ctx.handle)
     return rho
+
+
+def edm_sweep_ccm(X, lengths=None, E_max: int = E_MAX, tau: int = 1, rho=None,
+                  ctx: Context | None = None):
+    """E sweep (Tp = 1) then all-to-all CCM of the same series at the targets'
+    E* (Tp = 0).  Returns (rho_sweep [N][E_max], E_opt [N], rho [N][N])."""
+    ctx = ctx or default_context(X.device)
+    N, ldx = X.shape
+    L = _host_i64(np.full(N, ldx) if lengths is None else lengths, N, "lengths")
+    rho_s = torch.empty((N, E_max), dtype=torch.float32, device=X.device)
+    E_opt = torch.empty((N,), dtype=torch.int32, device=X.device)
+    if rho is None:
+        rho = torch.empty((N, N), dtype=torch.float32, device=X.device)
+    _check(load_library().edm_sweep_ccm(
+        ctx.handle, _dev_ptr(X, torch.float32, "X"), L.ctypes.data_as(_p), N, ldx, E_max, tau,
+        _dev_ptr(rho_s, torch.float32, "rho_sweep"), _dev_ptr(E_opt, torch.int32, "E_opt"),
+        _dev_ptr(rho, torch.float32, "rho")), ctx.handle)
+    return rho_s, E_opt, rho
 
 
 # ---------------------------------------------------------------- surrogate --
