@@ -34,6 +34,11 @@ if ROOT not in sys.path:
 # ceiling for this kernel is one op per lane per clock: 78.6 T ops/s.
 ALU_PEAK_OPS = 256 * 128 * 2.4e9
 
+# HBM bytes of one chosen-form sweep on this workload from rocprofv3 --pmc
+# FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0), the scales a 256 MiB device copy
+# gives the two counters (profiles/chosen_sweep_ccm_logistic1024_L5000.md).
+SWEEP_TRAFFIC_BYTES = 3.16e9
+
 WORKLOAD = dict(name="logistic-network", N=1024, L=5000, E_max=20, tau=1, Tp_sweep=1,
                 Tp_ccm=0, seed=2)
 
@@ -171,6 +176,9 @@ def main(argv=None):
                     help="all: time plain, batched and chosen forms; both: plain and chosen; "
                          "value is the last form's (the chosen form unless one form is asked for)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one device-to-device copy of 256 MiB, whose FETCH_SIZE / "
+                         "WRITE_SIZE counters scale the kernels' HBM byte counts")
     ap.add_argument("--cores", type=int, default=0, help="CPU baseline workers (0: min(16, cpus))")
     ap.add_argument("--workload", choices=("network", "uneven", "learned", "precision"),
                     default="network",
@@ -187,6 +195,13 @@ def main(argv=None):
     import torch
 
     from paper_2105_12301_amd import edm, synth
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     if args.workload == "uneven":
         print(json.dumps(bench_uneven(args, torch, edm, synth)))
@@ -259,7 +274,7 @@ def main(argv=None):
             "peak": ALU_PEAK_OPS / 1e12,
             "unit": "Top/s",
             "frac": achieved / ALU_PEAK_OPS,
-            "traffic": None,
+            "traffic": SWEEP_TRAFFIC_BYTES if main_form == edm.EDM_FORM_CHOSEN else None,
             "ops_per_sweep": ops,
         },
     }

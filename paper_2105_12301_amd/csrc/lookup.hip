@@ -1,14 +1,23 @@
 // Batched simplex lookup with the Pearson skill computed on the fly
 // (kEDM paper: Section 2.1 steps 3-4, Section 3.4 and Algorithm 3).
 //
-// One workgroup takes one library table and a tile of T targets that share
-// its embedding dimension.  The T target series are staged in LDS (only the
-// window [t(0)+Tp, t(nq-1)+Tp] the table can touch), so every neighbour gather
-// is an LDS read; each thread then walks query points p with a stride of 256,
-// reads the table row of p once and reuses it for all T targets.  Predictions
-// are written only on request; the co-moments of (observation, prediction)
-// are accumulated per thread as shifted float64 sums and merged across the
-// workgroup with the stable pairwise update, so rho needs no second pass.
+// A (library, target) pair is computed by one wave: its lanes walk the query
+// points p = lane, lane + 64, ..., read the table row of p (K indices and
+// weights), gather the K neighbours' futures of the target from LDS, and
+// accumulate float64 sums of the observation and the prediction, both
+// relative to the target's first staged sample (the weights sum to one, so
+// the prediction minus that sample is the weighted sum of the gathered
+// samples minus it; the float32 error stays proportional to the target's
+// spread).  The sums are reduced over the wave by a fixed butterfly, so a
+// pair's result does not depend on which kernel computed it or on how many
+// targets share the wave: the grid kernel, the work-list kernel of the plan
+// and every form are bit-identical.
+//
+// Grid kernel: a workgroup stages a tile of T targets of one E (the window
+// [t(0)+Tp, t(nq-1)+Tp] the tables can touch) and its 4 waves run 4
+// libraries' tables against them, each wave reusing every table row for the
+// T targets.  Work-list kernel: one item (library, T <= 4 targets) per
+// workgroup; wave w takes target w.
 #include <array>
 #include <utility>
 
@@ -19,53 +28,37 @@
 namespace edm {
 namespace {
 
-constexpr int kTMax = 8;               // targets per workgroup, upper bound
-constexpr int kItemTMax = 4;           // the same for work-list items (register budget)
+constexpr int kTMax = 8;               // targets per grid workgroup, upper bound
+constexpr int kItemTMax = kLookupItemMaxTargets;
+constexpr int kLookupWaves = kLookupThreads / kWave;
 constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS for staged targets
 
-// One workgroup's lookups: library `lib` with table (idx, w) [nq][K] at
-// dimension E, targets tgt_ids[t0 .. t0+T) of a list of ntgt (identity list
-// when tgt_ids is null).  Every early return is uniform across the workgroup.
-template <int K, int kTMax>
-__device__ __forceinline__ void lookup_body(const LookupArgs &a, const int E, const int lib,
-                                            const int32_t *__restrict__ tidx,
-                                            const float *__restrict__ tw,
-                                            const int32_t *__restrict__ tgt_ids, const int t0,
-                                            const int T, const int ntgt, float *__restrict__ ys) {
-  __shared__ Mom wmom[kLookupThreads / kWave][kTMax];
-  const int64_t Lx = a.Lx_dev ? a.Lx_dev[lib] : a.Lx_uni;
-  const int off = (E - 1) * a.tau + a.Tp;
-  const int m = static_cast<int>(Lx) - off;
-  if (m - 1 < K) return;  // the table does not exist for this library
-  if (t0 >= ntgt) return;
+struct Sums {
+  double so, sp, soo, spp, sop;
+};
 
-  int tgt[kTMax];
-  bool ok[kTMax];
-  bool bad = false;
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
-  for (int t = 0; t < kTMax; ++t) {
-    const int jt = t0 + t;
-    ok[t] = t < T && jt < ntgt;
-    tgt[t] = ok[t] ? (tgt_ids ? tgt_ids[jt] : jt) : 0;
-    if (ok[t] && a.Ly_dev && a.Ly_dev[tgt[t]] < Lx) ok[t] = false;  // pair undefined
-    if (ok[t]) {
-      const float *__restrict__ y = a.Y + static_cast<int64_t>(tgt[t]) * a.ldy + off;
-      for (int e = threadIdx.x; e < m; e += kLookupThreads) {
-        const float v = y[e];
-        bad |= !isfinite(v);
-        ys[t * m + e] = v;
-      }
-    }
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+// Skill sums of one wave for TW targets (ok[t] false: skipped) through the
+// table (tidx, tw) [m][K].  yt[t]: the target's staged window in LDS.
+// pred[t] (or null): prediction output row.
+template <int K, int TW>
+__device__ __forceinline__ void wave_pairs(const int32_t *__restrict__ tidx,
+                                           const float *__restrict__ tw, const int m,
+                                           const float *const (&yt)[TW], const bool (&ok)[TW],
+                                           float *const (&pred)[TW], Sums (&s)[TW]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  float ct[TW];
+#pragma unroll
+  for (int t = 0; t < TW; ++t) {
+    s[t] = Sums{0.0, 0.0, 0.0, 0.0, 0.0};
+    ct[t] = ok[t] ? yt[t][0] : 0.0f;
   }
-  if (bad) atomicOr(a.status, 1);
-  __syncthreads();
-
-  double c = 0.0;
-  double ro[kTMax], rp[kTMax], so[kTMax], sp[kTMax], soo[kTMax], spp[kTMax], sop[kTMax];
-#pragma unroll
-  for (int t = 0; t < kTMax; ++t) ro[t] = rp[t] = so[t] = sp[t] = soo[t] = spp[t] = sop[t] = 0.0;
-
-  for (int p = threadIdx.x; p < m; p += kLookupThreads) {
+  for (int p = lane; p < m; p += kWave) {
     int qi[K];
     float wi[K];
     const int64_t row = static_cast<int64_t>(p) * K;
@@ -75,123 +68,178 @@ __device__ __forceinline__ void lookup_body(const LookupArgs &a, const int E, co
       wi[i] = tw[row + i];
     }
 #pragma unroll
-    for (int t = 0; t < kTMax; ++t) {
+    for (int t = 0; t < TW; ++t) {
       if (ok[t]) {
-        // Predictions are accumulated relative to the target's first staged
-        // sample c: sum_i w_i (y_i - c) equals Yhat - c because the weights
-        // sum to one, and keeps the float32 error proportional to the
-        // target's spread rather than its level.
-        const float *yt = ys + t * m;
-        const float ct = yt[0];
+        const float *y = yt[t];
         float yh = 0.0f;
 #pragma unroll
-        for (int i = 0; i < K; ++i) yh = fmaf(wi[i], yt[qi[i]] - ct, yh);
-        const double o = static_cast<double>(yt[p]) - static_cast<double>(ct);
+        for (int i = 0; i < K; ++i) yh = fmaf(wi[i], y[qi[i]] - ct[t], yh);
+        const double o = static_cast<double>(y[p]) - static_cast<double>(ct[t]);
         const double ph = static_cast<double>(yh);
-        if (c == 0.0) {
-          ro[t] = o;
-          rp[t] = ph;
-        }
-        const double dO = o - ro[t], dP = ph - rp[t];
-        so[t] += dO;
-        sp[t] += dP;
-        soo[t] += dO * dO;
-        spp[t] += dP * dP;
-        sop[t] += dO * dP;
-        if (a.pred) a.pred[static_cast<int64_t>(tgt[t]) * a.ldpred + p] = yh + ct;
+        // explicit fused forms: the same operations in every instantiation
+        s[t].so += o;
+        s[t].sp += ph;
+        s[t].soo = fma(o, o, s[t].soo);
+        s[t].spp = fma(ph, ph, s[t].spp);
+        s[t].sop = fma(o, ph, s[t].sop);
+        if (pred[t]) pred[t][p] = yh + ct[t];
       }
     }
-    c += 1.0;
   }
+#pragma unroll
+  for (int t = 0; t < TW; ++t) {
+    if (ok[t]) {  // uniform across the wave
+      s[t].so = wave_sum(s[t].so);
+      s[t].sp = wave_sum(s[t].sp);
+      s[t].soo = wave_sum(s[t].soo);
+      s[t].spp = wave_sum(s[t].spp);
+      s[t].sop = wave_sum(s[t].sop);
+    }
+  }
+}
 
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+__device__ __forceinline__ float pair_rho(int m, const Sums &s) {
+  return static_cast<float>(
+      mom_rho(mom_from_shifted_sums(static_cast<double>(m), 0.0, 0.0, s.so, s.sp, s.soo, s.spp, s.sop)));
+}
+
+// Stage the window [off, off + n) of T targets into ys[t * ms + e], zero past
+// a target's own length.
+__device__ __forceinline__ void stage_targets(const LookupArgs &a, const int *tgt, int T, int off,
+                                              int n, int ms, float *ys) {
+  bool bad = false;
+  for (int t = 0; t < T; ++t) {
+    const int64_t Ly = a.Ly_dev ? a.Ly_dev[tgt[t]] : a.ldy;
+    const int n_t = static_cast<int>(Ly - off < n ? Ly - off : n);
+    const float *__restrict__ y = a.Y + static_cast<int64_t>(tgt[t]) * a.ldy + off;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+      float v = 0.0f;
+      if (e < n_t) {
+        v = y[e];
+        bad |= !isfinite(v);
+      }
+      ys[t * ms + e] = v;
+    }
+  }
+  if (bad) atomicOr(a.status, 1);
+}
+
+// Grid kernel: blockIdx.x = tile of T targets, blockIdx.y = group of 4
+// library slots; ms = LDS row stride (>= every staged window).
+template <int K>
+__global__ __launch_bounds__(kLookupThreads) void k_lookup(LookupArgs a, int T, int ms,
+                                                           int nslots, int slot0) {
+  extern __shared__ float ys[];  // [T][ms]
+  const int t0 = static_cast<int>(blockIdx.x) * T;
+  const int sbase = slot0 + static_cast<int>(blockIdx.y) * kLookupWaves;
+  const int off = (a.E - 1) * a.tau + a.Tp;
+  int tgt[kTMax];
+  const int Tn = a.ntgt - t0 < T ? a.ntgt - t0 : T;
+#pragma unroll
+  for (int t = 0; t < kTMax; ++t) tgt[t] = t < Tn ? (a.tgt_ids ? a.tgt_ids[t0 + t] : t0 + t) : 0;
+  int n_blk = 0;  // widest query range of the workgroup's libraries
+  for (int w = 0; w < kLookupWaves; ++w) {
+    const int slot = sbase + w;
+    if (slot >= slot0 + nslots) break;
+    const int lib = a.lib_ids ? a.lib_ids[slot] : slot;
+    const int64_t Lx = a.Lx_dev ? a.Lx_dev[lib] : a.Lx_uni;
+    const int mw = static_cast<int>(Lx) - off;
+    n_blk = mw > n_blk ? mw : n_blk;
+  }
+  if (n_blk - 1 < K) return;  // no table in this workgroup (uniform)
+  stage_targets(a, tgt, Tn, off, n_blk, ms, ys);
+  __syncthreads();
+
+  const int wave = static_cast<int>(threadIdx.x) / kWave;
+  const int slot = __builtin_amdgcn_readfirstlane(sbase + wave);
+  if (slot >= slot0 + nslots) return;
+  const int lib = a.lib_ids ? a.lib_ids[slot] : slot;
+  const int64_t Lx = a.Lx_dev ? a.Lx_dev[lib] : a.Lx_uni;
+  const int m = static_cast<int>(Lx) - off;
+  if (m - 1 < K) return;  // the table does not exist for this library
+  const int64_t tbl = static_cast<int64_t>(slot) * a.tbl_stride;
+  const float *yt[kTMax];
+  bool ok[kTMax];
+  float *pred[kTMax];
 #pragma unroll
   for (int t = 0; t < kTMax; ++t) {
-    if (t < T) {  // uniform
-      const Mom mt = mom_wave_reduce(
-          ok[t] ? mom_from_shifted_sums(c, ro[t], rp[t], so[t], sp[t], soo[t], spp[t], sop[t])
-                : mom_zero());
-      if (lane == 0) wmom[wave][t] = mt;
-    }
+    yt[t] = ys + t * ms;
+    ok[t] = t < Tn && !(a.Ly_dev && a.Ly_dev[tgt[t]] < Lx);  // pair defined
+    pred[t] = (ok[t] && a.pred) ? a.pred + static_cast<int64_t>(tgt[t]) * a.ldpred : nullptr;
   }
-  __syncthreads();
-  if (a.rho && static_cast<int>(threadIdx.x) < T) {
-    const int t = threadIdx.x;
-    const int jt = t0 + t;
-    if (jt < ntgt) {
-      Mom s = wmom[0][t];
+  Sums s[kTMax];
+  wave_pairs<K, kTMax>(a.idx + tbl, a.w + tbl, m, yt, ok, pred, s);
+  if (a.rho && (threadIdx.x & (kWave - 1)) == 0) {
 #pragma unroll
-      for (int w = 1; w < kLookupThreads / kWave; ++w) s = mom_merge(s, wmom[w][t]);
-      const int j = tgt_ids ? tgt_ids[jt] : jt;
-      const bool defined = !(a.Ly_dev && a.Ly_dev[j] < Lx);
-      if (defined) a.rho[static_cast<int64_t>(lib) * a.ldrho + j] = static_cast<float>(mom_rho(s));
-    }
+    for (int t = 0; t < kTMax; ++t)
+      if (ok[t]) a.rho[static_cast<int64_t>(lib) * a.ldrho + tgt[t]] = pair_rho(m, s[t]);
   }
 }
 
-template <int K>
-__global__ __launch_bounds__(kLookupThreads) void k_lookup(LookupArgs a, int T, int slot0) {
-  extern __shared__ float ys[];  // [T][m]
-  const int slot = slot0 + static_cast<int>(blockIdx.y);
-  const int lib = a.lib_ids ? a.lib_ids[slot] : slot;
-  const int64_t tbl = static_cast<int64_t>(slot) * a.tbl_stride;
-  lookup_body<K, kTMax>(a, a.E, lib, a.idx + tbl, a.w + tbl, a.tgt_ids,
-                        static_cast<int>(blockIdx.x) * T, T, a.ntgt, ys);
-}
-
-template <int K>
-__device__ __forceinline__ void lookup_item(const LookupArgs &a, const LookupItem &w, float *ys) {
-  const int64_t o = a.tbl_off[static_cast<int64_t>(w.lib) * (EDM_E_MAX + 1) + w.E];
-  lookup_body<K, kItemTMax>(a, w.E, w.lib, a.tbl_idx + o, a.tbl_w + o,
-                            a.bucket_ids + a.bucket_at[w.E], w.first, w.T, w.first + w.count, ys);
-}
-
-// Item kernel for one E (K = E + 1): persistent (counter != nullptr: loop
-// pulling items) or one workgroup per item.  Item fields are made
-// wave-uniform.
+// Work-list kernel for one E (K = E + 1): persistent (counter != nullptr:
+// workgroups pull items) or one workgroup per item.  Item fields are made
+// wave-uniform; wave w computes the item's target w.
 template <int K>
 __global__ __launch_bounds__(kLookupThreads) void k_lookup_items(LookupArgs a,
                                                                 const LookupItem *__restrict__ items,
                                                                 int n_items, int *counter) {
   extern __shared__ float ys[];
   __shared__ int item_s;
-  // One call site for the body (a second one would make the inliner emit a
-  // real call with a scratch frame).  Without a counter each workgroup runs
-  // the item of its own index once.
+  const int E = K - 1;
+  const int off = (E - 1) * a.tau + a.Tp;
   for (int trip = 0;; ++trip) {
     int it;
     if (counter == nullptr) {
       if (trip > 0) break;
       it = static_cast<int>(blockIdx.x);
     } else {
-      __syncthreads();
+      __syncthreads();  // the previous item is done with ys and item_s
       if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
       __syncthreads();
       it = __builtin_amdgcn_readfirstlane(item_s);
       if (it >= n_items) break;
     }
-    LookupItem w;
-    w.lib = __builtin_amdgcn_readfirstlane(items[it].lib);
-    w.E = static_cast<int16_t>(K - 1);
-    w.T = static_cast<int16_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(items[it].T)));
-    w.first = __builtin_amdgcn_readfirstlane(items[it].first);
-    w.count = __builtin_amdgcn_readfirstlane(items[it].count);
-    lookup_item<K>(a, w, ys);
+    const int lib = __builtin_amdgcn_readfirstlane(items[it].lib);
+    const int T = __builtin_amdgcn_readfirstlane(static_cast<int>(items[it].T));
+    const int first = __builtin_amdgcn_readfirstlane(items[it].first);
+    const int count = __builtin_amdgcn_readfirstlane(items[it].count);
+    const int64_t Lx = a.Lx_dev ? a.Lx_dev[lib] : a.Lx_uni;
+    const int m = static_cast<int>(Lx) - off;
+    const int32_t *ids = a.bucket_ids + a.bucket_at[E];
+    const int Tn = count < T ? count : T;
+    int tgt[kItemTMax];
+#pragma unroll
+    for (int t = 0; t < kItemTMax; ++t) tgt[t] = t < Tn ? ids[first + t] : 0;
+    const bool has = m - 1 >= K;  // uniform
+    __syncthreads();  // ys is free
+    if (has) stage_targets(a, tgt, Tn, off, m, m, ys);
+    __syncthreads();
+    const int wave = static_cast<int>(threadIdx.x) / kWave;
+    if (has && wave < Tn) {  // uniform per wave
+      const int64_t o = a.tbl_off[static_cast<int64_t>(lib) * (EDM_E_MAX + 1) + E];
+      const float *yt[1] = {ys + wave * m};
+      const bool ok[1] = {!(a.Ly_dev && a.Ly_dev[tgt[wave]] < Lx)};
+      float *const pred[1] = {nullptr};
+      Sums s[1];
+      wave_pairs<K, 1>(a.tbl_idx + o, a.tbl_w + o, m, yt, ok, pred, s);
+      if (a.rho && ok[0] && (threadIdx.x & (kWave - 1)) == 0)
+        a.rho[static_cast<int64_t>(lib) * a.ldrho + tgt[wave]] = pair_rho(m, s[0]);
+    }
   }
 }
 
-using LaunchFn = hipError_t (*)(const LookupArgs &, dim3, size_t, int, int, hipStream_t);
+using LaunchFn = hipError_t (*)(const LookupArgs &, dim3, size_t, int, int, int, int, hipStream_t);
 
 template <int K>
-hipError_t launch_k(const LookupArgs &a, dim3 grid, size_t shm, int T, int slot0,
-                    hipStream_t st) {
+hipError_t launch_k(const LookupArgs &a, dim3 grid, size_t shm, int T, int ms, int nslots,
+                    int slot0, hipStream_t st) {
   const void *fn = reinterpret_cast<const void *>(&k_lookup<K>);
   if (shm > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(shm));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_lookup<K>), grid, dim3(kLookupThreads), shm, st, a, T, slot0);
+  hipLaunchKernelGGL((k_lookup<K>), grid, dim3(kLookupThreads), shm, st, a, T, ms, nslots, slot0);
   return hipGetLastError();
 }
 
@@ -209,12 +257,14 @@ hipError_t launch_lookup(const LookupArgs &a, int nslots, int64_t m_max, hipStre
   if (T < 1) T = 1;
   if (T > kTMax) T = kTMax;
   if (T > a.ntgt) T = a.ntgt;
+  const int ms = static_cast<int>(m_max);
   const size_t shm = static_cast<size_t>(T) * static_cast<size_t>(m_max) * sizeof(float);
   const unsigned gx = static_cast<unsigned>((a.ntgt + T - 1) / T);
-  constexpr int kMaxY = 32768;
+  constexpr int kMaxY = 32768 * kLookupWaves;
   for (int s0 = 0; s0 < nslots; s0 += kMaxY) {
-    const int ny = nslots - s0 < kMaxY ? nslots - s0 : kMaxY;
-    hipError_t e = table[a.k - 1](a, dim3(gx, static_cast<unsigned>(ny)), shm, T, s0, st);
+    const int ns = nslots - s0 < kMaxY ? nslots - s0 : kMaxY;
+    const unsigned gy = static_cast<unsigned>((ns + kLookupWaves - 1) / kLookupWaves);
+    hipError_t e = table[a.k - 1](a, dim3(gx, gy), shm, T, ms, ns, s0, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
