@@ -40,14 +40,19 @@ int hip_err(edm_ctx *ctx, hipError_t e, const char *what) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Upper bound for the workspace (bytes); EDM_WORKSPACE_LIMIT overrides.
+// Upper bound for the workspace (bytes): half of the current device's
+// memory (at least 8 GiB); EDM_WORKSPACE_LIMIT overrides.
 size_t workspace_limit() {
   const char *s = std::getenv("EDM_WORKSPACE_LIMIT");
   if (s && *s) {
     const long long v = std::atoll(s);
     if (v > 0) return static_cast<size_t>(v);
   }
-  return size_t(8) << 30;
+  size_t free_b = 0, total_b = 0;
+  size_t lim = size_t(8) << 30;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && total_b / 2 > lim) lim = total_b / 2;
+  (void)hipGetLastError();
+  return lim;
 }
 
 // Make sure the workspace holds `bytes`.  Growing it waits for the stream so
@@ -383,12 +388,12 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
     tbl_bytes = std::max(tbl_bytes, static_cast<size_t>(m1 + 1) * (E + 1) * 8 * static_cast<size_t>(N));
   }
   const size_t off_tbl = plan.take(tbl_bytes);
-  const bool fused = (ctx->form == EDM_FORM_CHOSEN) && tau == 1 && plan.bytes <= workspace_limit();
+  bool fused = (ctx->form == EDM_FORM_CHOSEN) && tau == 1 && plan.bytes <= workspace_limit();
+  if (fused && ws_reserve(ctx, plan.bytes) != EDM_OK) fused = false;  // too large to allocate
   if (!fused) {  // the sweep, then the cross map at the selected E (Tp = 0)
     EDM_RC(edm_simplex_sweep(ctx, X, L, N, ldx, E_max, tau, 1, rho_sweep, E_opt));
     return edm_ccm(ctx, X, L, N, ldx, X, L, N, ldx, E_opt, tau, 0, rho);
   }
-  EDM_RC(ws_reserve(ctx, plan.bytes));
   int64_t *L_dev = reinterpret_cast<int64_t *>(ctx->ws + off_L);
   int32_t *ids_dev = reinterpret_cast<int32_t *>(ctx->ws + off_ids);
   edm::Mom *mom = reinterpret_cast<edm::Mom *>(ctx->ws + off_mom);
