@@ -204,7 +204,7 @@ typedef struct edm_plan edm_plan;
 typedef struct {
   int32_t tables_wg_per_cu;   /* 0: one workgroup per table item; >0: persistent workgroups per CU */
   int32_t lookup_wg_per_cu;   /* 0: one workgroup per lookup item; >0: persistent workgroups per CU */
-  int32_t lookup_targets;     /* targets staged per lookup workgroup, 1..4 */
+  int32_t lookup_targets;     /* targets staged per lookup workgroup, 1..16 */
 } edm_tune;
 
 void edm_tune_default(edm_tune *tune);

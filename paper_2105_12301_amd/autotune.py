@@ -18,7 +18,7 @@ from . import edm
 
 CANDIDATES = [
     dict(tables_wg_per_cu=t, lookup_wg_per_cu=l, lookup_targets=T)
-    for t in (0, 1, 2) for l in (0, 4) for T in (2, 4)
+    for t in (0, 1, 2) for l in (0, 4) for T in (4, 8, 16)
 ]
 
 

@@ -77,7 +77,9 @@ static_assert(kGramWaves * 32 == kKnnThreads, "a workgroup covers one query bloc
 constexpr float kGramScale = 1.0f - 0x1p-12f;  // s = 1 - 2^-12
 constexpr float kGramFloor = 0x1p-90f;          // absolute slack: flushed tiny products
 constexpr float kGramSafeMax = 0x1p56f;         // larger |x - mu| switches the filter off
-constexpr int kQueueCap = 32;                   // queued survivors per lane before a re-rank
+constexpr int kQueueCap = 16;                   // queued tile masks per lane before a re-rank
+constexpr float kGramBig = 0x1p120f;            // |threshold| cap: finite BF16 operands
+constexpr int kPass1Step = 2;                   // pass 1 looks at every kPass1Step-th tile
 
 __device__ __forceinline__ uint32_t bf16_bits(float f) {  // round to nearest even (finite f)
   const uint32_t u = __float_as_uint(f);
@@ -143,45 +145,65 @@ __device__ __forceinline__ f32x16_t mfma(const uint32_t (&a)[4], const uint32_t 
                                                  __builtin_bit_cast(bf16x8_t, bv), c, 0, 0, 0);
 }
 
+// K-slot layout of a group [ELO, EHI].  The last chunk ends with one norm
+// slot per E of the group and one threshold slot; a group whose lags, norms
+// and threshold do not fit one 16-slot chunk uses a shared first chunk of
+// lags 0..S-1 (S <= ELO, the same for every E of the group).
 template <int ELO, int EHI>
 struct Layout {
   static constexpr int kLo = ELO;
   static constexpr int NG = EHI - ELO + 1;
-  static constexpr bool kShared = ELO >= 16;  // chunk 0 = lags 0..15, the same for every E
-  static constexpr int kChunks = (EHI + NG + 15) / 16;
+  static constexpr bool kShared = EHI + NG + 1 > 16;
+  static constexpr int S = kShared ? (ELO < 16 ? ELO : 16) : 0;  // lags of the shared chunk
+  static constexpr int kChunks = kShared ? 2 : 1;
   static constexpr int kFirst = kShared ? 1 : 0;  // first chunk that depends on E
+  static constexpr int kLast = kChunks - 1;
+  static constexpr int kNorm = EHI - S;           // first norm slot of the last chunk
+  static constexpr int kT = kNorm + NG;           // threshold slot of the last chunk
   static_assert(ELO >= kGramEMin && EHI <= EDM_E_MAX && ELO <= EHI, "E range");
-  static_assert(kShared ? kChunks == 2 : kChunks == 1, "E range does not fit the slot layout");
-  // 0: zero slot, 1: lag s, 2 + g: norm slot of E = ELO + g
-  static constexpr int kind(int s) { return s < EHI ? 1 : (s < EHI + NG ? 2 + (s - EHI) : 0); }
+  static_assert(kT < 16, "E range does not fit the slot layout");
+  // Lag held by slot s of chunk C (-1: not a lag slot).
+  static constexpr int lag(int C, int s) {
+    if (kShared && C == 0) return s < S ? s : -1;
+    return s < kNorm ? S + s : -1;
+  }
+  // 0: zero, 1: lag, 2 + g: norm of E = ELO + g, 2 + NG: threshold
+  static constexpr int kind(int C, int s) {
+    if (lag(C, s) >= 0) return 1;
+    if (C != kLast) return 0;
+    if (s >= kNorm && s < kT) return 2 + (s - kNorm);
+    return s == kT ? 2 + NG : 0;
+  }
+  static constexpr int first_lag(int C) { return (kShared && C == 1) ? S : 0; }
 };
 
-// Candidate-side words of chunk C: lane half h1 holds slots 16C + 8h1 .. +7.
+// Candidate-side words of chunk C: lane half h1 holds slots 8 h1 .. 8 h1 + 7.
+// wh/wl: the window of samples first_lag(C) + 8 h1 .. + 7 of the candidate.
 template <class Lay, int C>
 __device__ __forceinline__ void build_a(uint32_t (&ah)[4], uint32_t (&al)[4],
                                         const uint32_t (&wh)[4], const uint32_t (&wl)[4],
                                         const uint32_t (&nr)[Lay::NG], bool h1) {
+  constexpr uint32_t kOne = 0x3f80u;  // BF16 1.0
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
     uint32_t vh[2], vl[2];
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) {
-      const int s0 = 16 * C + 8 * hh + 2 * w;
-      const int k0 = Lay::kind(s0), k1 = Lay::kind(s0 + 1);
       uint32_t h = 0, l = 0;
-      if (k0 == 1) {
-        h = wh[w] & 0xffffu;
-        l = wl[w] & 0xffffu;
-      } else if (k0 >= 2) {
-        h = nr[k0 - 2] & 0xffffu;
-        l = nr[k0 - 2] >> 16;
-      }
-      if (k1 == 1) {
-        h |= wh[w] & 0xffff0000u;
-        l |= wl[w] & 0xffff0000u;
-      } else if (k1 >= 2) {
-        h |= nr[k1 - 2] << 16;
-        l |= nr[k1 - 2] & 0xffff0000u;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int k = Lay::kind(C, 8 * hh + 2 * w + u);
+        const int sh = 16 * u;
+        const uint32_t m = 0xffffu << sh;
+        if (k == 1) {
+          h |= wh[w] & m;
+          l |= wl[w] & m;
+        } else if (k >= 2 && k < 2 + Lay::NG) {
+          h |= (nr[k - 2] & 0xffffu) << sh;
+          l |= (nr[k - 2] >> 16) << sh;
+        } else if (k == 2 + Lay::NG) {
+          h |= kOne << sh;
+        }
       }
       vh[hh] = h;
       vl[hh] = l;
@@ -192,28 +214,28 @@ __device__ __forceinline__ void build_a(uint32_t (&ah)[4], uint32_t (&al)[4],
 }
 
 // Query-side words of chunk C for dimension E: lags below E (already scaled
-// by -2), one in E's norm slot (hi operand only), zeros elsewhere.
+// by -2), one in E's norm slot (hi operand only), zeros elsewhere; the
+// threshold slot is written by set_threshold.
 template <class Lay, int C, int E>
 __device__ __forceinline__ void build_b(uint32_t (&bh)[4], uint32_t (&bl)[4],
                                         const uint32_t (&qh)[4], const uint32_t (&ql)[4],
                                         bool h1) {
-  constexpr uint32_t kOne = 0x3f80u;  // BF16 1.0
+  constexpr uint32_t kOne = 0x3f80u;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
     uint32_t vh[2], vl[2];
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) {
-      const int s0 = 16 * C + 8 * hh + 2 * w;
       uint32_t h = 0, l = 0;
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int s = s0 + u;
-        const int k = Lay::kind(s);
+        const int s = 8 * hh + 2 * w + u;
+        const int k = Lay::kind(C, s);
         const uint32_t m = u ? 0xffff0000u : 0xffffu;
-        if (k == 1 && s < E) {
+        if (k == 1 && Lay::lag(C, s) < E) {
           h |= qh[w] & m;
           l |= ql[w] & m;
-        } else if (k >= 2 && k - 2 == E - Lay::kLo) {
+        } else if (k == 2 + (E - Lay::kLo)) {
           h |= u ? (kOne << 16) : kOne;
         }
       }
@@ -223,6 +245,55 @@ __device__ __forceinline__ void build_b(uint32_t (&bh)[4], uint32_t (&bl)[4],
     bh[w] = h1 ? vh[1] : vh[0];
     bl[w] = h1 ? vl[1] : vl[0];
   }
+}
+
+// BF16 bits of f rounded toward -inf (finite f).
+__device__ __forceinline__ uint32_t bf16_bits_down(float f) {
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t t = u >> 16;
+  return ((u & 0x80000000u) && (u & 0xffffu)) ? t + 1u : t;
+}
+
+// Threshold slot of a query operand: -T as hi + lo with hi + lo <= -T, so the
+// product chain yields D - T' with T' >= T (never fewer survivors).
+template <class Lay>
+__device__ __forceinline__ void set_threshold(uint32_t (&bh)[4], uint32_t (&bl)[4], float T,
+                                              bool h1) {
+  constexpr int s = Lay::kT;
+  constexpr int w = (s & 7) >> 1;
+  constexpr int sh = 16 * (s & 1);
+  constexpr uint32_t m = 0xffffu << sh;
+  const float u = -T;
+  const uint32_t hi = bf16_bits(u);
+  const uint32_t lo = bf16_bits_down(u - bf16_val(hi));
+  if (h1 == ((s >> 3) != 0)) {
+    bh[w] = (bh[w] & ~m) | (hi << sh);
+    bl[w] = (bl[w] & ~m) | (lo << sh);
+  }
+}
+
+// Sign bits of 16 estimates, value v = 4 j + b at bit 8 j + 4 + b (so the
+// lowest set bit is the lowest candidate); bits 0-3 of every byte are zero.
+__device__ __forceinline__ uint32_t sign_mask(const uint32_t (&e)[16]) {
+  uint32_t d[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    // bytes: top byte of e[b], e[4 + b] | e[8 + b], e[12 + b]
+    const uint32_t p0 = __builtin_amdgcn_perm(e[4 + b], e[b], 0x0c0c0703u);
+    const uint32_t p1 = __builtin_amdgcn_perm(e[12 + b], e[8 + b], 0x0c0c0703u);
+    d[b] = __builtin_amdgcn_perm(p1, p0, 0x05040100u);  // byte j: value 4 j + b
+  }
+  return (d[3] & 0x80808080u) | ((d[2] >> 1) & 0x40404040u) | ((d[1] >> 2) & 0x20202020u) |
+         ((d[0] >> 3) & 0x10101010u);
+}
+constexpr uint32_t kSignBits = 0xf0f0f0f0u;
+
+// Tile index spread over the low nibbles of the first three bytes.
+__device__ __forceinline__ uint32_t tile_code(uint32_t t) {
+  return (t & 15u) | ((t & 0xf0u) << 4) | ((t & 0xf00u) << 8);
+}
+__device__ __forceinline__ uint32_t tile_of(uint32_t code) {
+  return (code & 15u) | ((code >> 4) & 0xf0u) | ((code >> 8) & 0xf00u);
 }
 
 // Insertion of a partner-list entry: lexicographic on (key, index) with the
@@ -270,7 +341,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   uint16_t *xl = xh + ld;
   const uint32_t *xh32 = reinterpret_cast<const uint32_t *>(xh);
   const uint32_t *xl32 = reinterpret_cast<const uint32_t *>(xl);
-  uint16_t *qbuf_all = xl + ld;  // [wave][kQueueCap][64] survivor queues
+  uint32_t *qbuf_all = reinterpret_cast<uint32_t *>(xl + ld);  // [wave][kQueueCap][64] queues
   const float mu = a.gram_mu[row];
   const uint32_t *__restrict__ nrm =
       a.gram_nrm + (static_cast<int64_t>(row) * kGramNE + (ELO - kGramEMin)) * ld;
@@ -307,10 +378,12 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
 
   float qk[TOT];
   int qi[TOT];
+  bool act_any = false;
   static_for<ELO, EHI>([&](auto EC) {
     constexpr int E = decltype(EC)::value;
     constexpr int OFF = list_off<ELO>(E);
     const bool act = p < L - (E - 1) - Tp && (a.mom != nullptr || ((need >> (E - 1)) & 1u));
+    act_any = act_any || act;
 #pragma unroll
     for (int i = 0; i < E + 1; ++i) {
       qk[OFF + i] = act ? __builtin_inff() : -1.0f;
@@ -318,30 +391,26 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     }
   });
 
-  // Query norms s N_E(p) and the thresholds T_E = kth_E - s N_E(p).
-  float nq[NG], thr[NG];
+  // Query norms s N_E(p); T_E = kth_E - s N_E(p) rides in the threshold slot.
+  float nq[NG];
 #pragma unroll
   for (int g = 0; g < NG; ++g) nq[g] = unpack_sum(nrm[g * ld + pc]);
 
-  // Query operands (fixed for the scan).
+  // Query operands (fixed between threshold updates).
   uint32_t bsh[4], bsl[4];
   uint32_t bh[NG][NCH - C0][4], bl[NG][NCH - C0][4];
   static_for<0, NCH - 1>([&](auto CC) {
     constexpr int C = decltype(CC)::value;
     uint32_t qh[4], ql[4];
-    read_window(xh32, pc + 16 * C + (h1 ? 8 : 0), qh);
-    read_window(xl32, pc + 16 * C + (h1 ? 8 : 0), ql);
+    read_window(xh32, pc + Lay::first_lag(C) + (h1 ? 8 : 0), qh);
+    read_window(xl32, pc + Lay::first_lag(C) + (h1 ? 8 : 0), ql);
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
       qh[w] = scale_m2(qh[w]);
       ql[w] = scale_m2(ql[w]);
     }
     if constexpr (Lay::kShared && C == 0) {
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        bsh[w] = qh[w];
-        bsl[w] = ql[w];
-      }
+      build_b<Lay, 0, EHI>(bsh, bsl, qh, ql, h1);
     } else {
       static_for<ELO, EHI>([&](auto EC) {
         constexpr int E = decltype(EC)::value;
@@ -362,17 +431,17 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     for (int g = 0; g < NG; ++g) nr_next[g] = nrm[g * ld + c0 + n];
   };
   // HI_ONLY (pass 1) builds just the hi operands and the hi*hi product.
-  auto load_tile = [&](int c0, auto hi_only) {
+  auto load_tile = [&](int c0, int c_next, auto hi_only) {
     constexpr bool HI_ONLY = decltype(hi_only)::value;
     const int qa = c0 + n;
 #pragma unroll
     for (int g = 0; g < NG; ++g) nr[g] = nr_next[g];
-    fetch(c0 + 32);  // in bounds: the norm rows hold gram_ld >= L + 64 entries
+    fetch(c_next < m_lo ? c_next : c0);  // in bounds: c0 < m_lo and gram_ld >= L + 64
     static_for<0, NCH - 1>([&](auto CC) {
       constexpr int C = decltype(CC)::value;
       uint32_t wh[4], wl[4] = {0u, 0u, 0u, 0u};
-      read_window(xh32, qa + 16 * C + (h1 ? 8 : 0), wh);
-      if constexpr (!HI_ONLY) read_window(xl32, qa + 16 * C + (h1 ? 8 : 0), wl);
+      read_window(xh32, qa + Lay::first_lag(C) + (h1 ? 8 : 0), wh);
+      if constexpr (!HI_ONLY) read_window(xl32, qa + Lay::first_lag(C) + (h1 ? 8 : 0), wl);
       build_a<Lay, C>(ah[C], al[C], wh, wl, nr, h1);
     });
     acc_s = f32x16_t{};
@@ -435,8 +504,8 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     }
     fetch(0);
 #pragma unroll 1
-    for (int c0 = 0; c0 < m_lo; c0 += 32) {
-      load_tile(c0, std::true_type{});
+    for (int c0 = 0; c0 < m_lo; c0 += 32 * kPass1Step) {
+      load_tile(c0, c0 + 32 * kPass1Step, std::true_type{});
       const f32x16_t acc = estimate_hi();
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -467,28 +536,43 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     });
   }
 
-  // Pass 2: survivors of each tile (estimate within the margin of the
-  // threshold for some E) are queued per lane in LDS in ascending candidate
-  // order and re-ranked in batches, so the lists change only at a flush.
-  uint16_t *qbuf = qbuf_all + wave * (kQueueCap * kWave) + lane;  // entry i at qbuf[i * 64]
-  int cnt = 0;
+  // Pass 2: every E's threshold rides in the products, so the estimate of
+  // E is D - T and a candidate survives where the minimum over the group's E
+  // is negative.  A tile's survivors are one sign mask per lane, queued in
+  // LDS with the tile index when not empty (no branch) and re-ranked in
+  // batches, so the lists change only at a flush.
+  uint32_t *qbuf = qbuf_all + wave * (kQueueCap * kWave) + lane;  // entry i at qbuf[i * 64]
+  int cnt = 0;   // queued entries
+  int nsv = 0;   // queued survivors
   auto refresh = [&]() {
     static_for<ELO, EHI>([&](auto EC) {
       constexpr int E = decltype(EC)::value;
+      constexpr int g = E - ELO;
       const float own = qk[list_off<ELO>(E) + E];
-      const float kth = fminf(fminf(own, __shfl_xor(own, 32)), ub[E - ELO]);
-      thr[E - ELO] = own < 0.0f ? -__builtin_inff()
-                                : (unsafe ? __builtin_inff() : (kth - nq[E - ELO]) + kGramFloor);
+      const float kth = fminf(fminf(own, __shfl_xor(own, 32)), ub[g]);
+      const float T = own < 0.0f ? -kGramBig : fminf((kth - nq[g]) + kGramFloor, kGramBig);
+      set_threshold<Lay>(bh[g][NCH - 1 - C0], bl[g][NCH - 1 - C0], T, h1);
     });
   };
-  // Re-rank the queued candidates: uniform trip count and a branch-free body
-  // keep the lists in place in registers.
+  // Re-rank the queued candidates, lowest first: uniform trip count and a
+  // branch-free body keep the lists in place in registers.
   auto flush = [&]() {
-    const int n_iter = wave_max(cnt);
+    const int n_iter = wave_max(nsv);
+    int j = 0;
+    uint32_t cur = qbuf[0];
+    uint32_t nxt = qbuf[kWave];
 #pragma unroll 1
     for (int it = 0; it < n_iter; ++it) {
-      const bool has = it < cnt;
-      const int q = has ? static_cast<int>(qbuf[it * kWave]) : 0;
+      const bool has = it < nsv;
+      const bool adv = (cur & kSignBits) == 0u;  // entry done: the next one holds the next survivor
+      cur = adv ? nxt : cur;
+      j += adv ? 1 : 0;
+      nxt = qbuf[(j + 1 < kQueueCap ? j + 1 : j) * kWave];
+      const uint32_t bit = cur & kSignBits;
+      const int pos = bit ? __builtin_ctz(bit) : 0;
+      cur ^= bit ? (1u << pos) : 0u;
+      const int qq = static_cast<int>(tile_of(cur)) * 32 + (pos & ~7) + (pos & 3) + (h1 ? 4 : 0);
+      const int q = has ? qq : 0;
       float key[NG];
       exact_keys(q, has && q != p, key);
       static_for<ELO, EHI>([&](auto EC) {
@@ -502,38 +586,30 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
       });
     }
     cnt = 0;
+    nsv = 0;
     refresh();
   };
   refresh();
   if (pw < m_lo) {
     fetch(0);
+    const bool pass_all = unsafe && act_any;  // filter off: every candidate is re-ranked
 #pragma unroll 1
     for (int c0 = 0; c0 < m_lo; c0 += 32) {
-      load_tile(c0, std::false_type{});
-      bool surv[16];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) surv[v] = false;
+      load_tile(c0, c0 + 32, std::false_type{});
+      // Only the sign of the minimum over E matters: OR of the sign bits.
+      uint32_t e[16];
       static_for<0, NG - 1>([&](auto GC) {
         constexpr int g = decltype(GC)::value;
         const f32x16_t acc = estimate(g);
 #pragma unroll
-        for (int v = 0; v < 16; ++v) surv[v] = surv[v] || !(acc[v] > thr[g]);
+        for (int v = 0; v < 16; ++v) e[v] = (g == 0 ? 0u : e[v]) | __float_as_uint(acc[v]);
       });
-      bool any = false;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) any = any || surv[v];
-      if (__builtin_amdgcn_ballot_w64(any)) {
-        uint32_t bits = 0;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) bits |= surv[v] ? (1u << v) : 0u;
-        if (__builtin_amdgcn_ballot_w64(cnt + __builtin_popcount(bits) > kQueueCap)) flush();
-        while (bits) {
-          const int v = __builtin_ctz(bits);
-          bits &= bits - 1u;
-          qbuf[cnt * kWave] = static_cast<uint16_t>(c0 + 8 * (v >> 2) + (h1 ? 4 : 0) + (v & 3));
-          ++cnt;
-        }
-      }
+      uint32_t bits = sign_mask(e);
+      if (unsafe) bits = pass_all ? kSignBits : 0u;
+      qbuf[cnt * kWave] = bits | tile_code(static_cast<uint32_t>(c0) >> 5);
+      cnt += bits != 0u;
+      nsv += __builtin_popcount(bits);
+      if (__builtin_amdgcn_ballot_w64(cnt == kQueueCap)) flush();
     }
   }
   flush();
@@ -639,18 +715,20 @@ constexpr GramFn gram_fn() {
 GramFn pick(int lo, int hi) {
   switch (lo) {
     case 9: {
-      constexpr GramFn t[] = {gram_fn<9, 9>(), gram_fn<9, 10>(), gram_fn<9, 11>(), gram_fn<9, 12>()};
-      return hi >= 9 && hi <= 12 ? t[hi - 9] : nullptr;
+      constexpr GramFn t[] = {gram_fn<9, 9>(), gram_fn<9, 10>(), gram_fn<9, 11>()};
+      return hi >= 9 && hi <= 11 ? t[hi - 9] : nullptr;
     }
-    case 13: {
-      constexpr GramFn t[] = {gram_fn<13, 13>(), gram_fn<13, 14>()};
-      return hi >= 13 && hi <= 14 ? t[hi - 13] : nullptr;
+    case 12: {
+      constexpr GramFn t[] = {gram_fn<12, 12>(), gram_fn<12, 13>()};
+      return hi >= 12 && hi <= 13 ? t[hi - 12] : nullptr;
     }
-    case 15:
-      return hi == 15 ? gram_fn<15, 15>() : nullptr;
-    case 16: {
-      constexpr GramFn t[] = {gram_fn<16, 16>(), gram_fn<16, 17>(), gram_fn<16, 18>()};
-      return hi >= 16 && hi <= 18 ? t[hi - 16] : nullptr;
+    case 14: {
+      constexpr GramFn t[] = {gram_fn<14, 14>(), gram_fn<14, 15>(), gram_fn<14, 16>()};
+      return hi >= 14 && hi <= 16 ? t[hi - 14] : nullptr;
+    }
+    case 17: {
+      constexpr GramFn t[] = {gram_fn<17, 17>(), gram_fn<17, 18>()};
+      return hi >= 17 && hi <= 18 ? t[hi - 17] : nullptr;
     }
     case 19: {
       constexpr GramFn t[] = {gram_fn<19, 19>(), gram_fn<19, 20>()};
@@ -681,7 +759,7 @@ hipError_t launch_gram_group(const KnnArgs &a, int lo, int hi, int nslots, int64
   if (fn == nullptr || L_max > kGramLMax || a.gram_ld < L_max + kGramPad || a.tau != 1)
     return hipErrorInvalidValue;
   const size_t shm = static_cast<size_t>(a.gram_ld) * (sizeof(float) + 2 * sizeof(uint16_t)) +
-                     sizeof(uint16_t) * kQueueCap * kGramThreads;
+                     sizeof(uint32_t) * kQueueCap * kGramThreads;
   const void *f = reinterpret_cast<const void *>(fn);
   if (shm > 65536) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -68,7 +68,7 @@ struct TableItem {
 
 // Work item of the persistent lookup kernel: a tile of targets of one E for
 // one library (targets bucket_ids[bucket_at[E] + tile*T ...]).
-constexpr int kLookupItemMaxTargets = 4;  // T of a LookupItem is at most this
+constexpr int kLookupItemMaxTargets = 16;  // T of a LookupItem is at most this
 struct LookupItem {
   int32_t lib;
   int16_t E;
@@ -91,6 +91,9 @@ constexpr int kGramEMin = 9;
 constexpr int kGramNE = EDM_E_MAX - kGramEMin + 1;
 constexpr int kGramPad = 64;  // zero samples staged past the end of a series
 constexpr int64_t kGramLMax = 14336;
+// E groups of the filtered scan (one register list per E of a group; the
+// slot layout needs E_hi + |group| + 1 <= 16 or a shared first chunk).
+constexpr int kGramGroups[5][2] = {{9, 11}, {12, 13}, {14, 16}, {17, 18}, {19, 20}};
 inline int64_t gram_ld(int64_t L_max) { return (L_max + kGramPad + 63) / 64 * 64; }
 // Per slot: centring constant, then the packed norms of every E >= kGramEMin.
 hipError_t launch_gram_prep(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t st);

@@ -16,8 +16,8 @@
 // Grid kernel: a workgroup stages a tile of T targets of one E (the window
 // [t(0)+Tp, t(nq-1)+Tp] the tables can touch) and its 4 waves run 4
 // libraries' tables against them, each wave reusing every table row for the
-// T targets.  Work-list kernel: one item (library, T <= 4 targets) per
-// workgroup; wave w takes target w.
+// T targets.  Work-list kernel: one item (library, T <= 16 targets) per
+// workgroup; wave w takes targets 4w .. 4w+3 in one table pass.
 #include <array>
 #include <utility>
 
@@ -30,6 +30,7 @@ namespace {
 
 constexpr int kTMax = 8;               // targets per grid workgroup, upper bound
 constexpr int kItemTMax = kLookupItemMaxTargets;
+constexpr int kWaveT = kItemTMax / (kLookupThreads / 64);  // targets per wave in an item
 constexpr int kLookupWaves = kLookupThreads / kWave;
 constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS for staged targets
 
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup(LookupArgs a, int T, 
 
 // Work-list kernel for one E (K = E + 1): persistent (counter != nullptr:
 // workgroups pull items) or one workgroup per item.  Item fields are made
-// wave-uniform; wave w computes the item's target w.
+// wave-uniform; wave w computes the item's targets 4w .. 4w+3.
 template <int K>
 __global__ __launch_bounds__(kLookupThreads) void k_lookup_items(LookupArgs a,
                                                                 const LookupItem *__restrict__ items,
@@ -214,16 +215,28 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup_items(LookupArgs a,
     __syncthreads();  // ys is free
     if (has) stage_targets(a, tgt, Tn, off, m, m, ys);
     __syncthreads();
+    // wave w: targets w*kWaveT .. +kWaveT-1 of the item, one table pass
     const int wave = static_cast<int>(threadIdx.x) / kWave;
-    if (has && wave < Tn) {  // uniform per wave
+    const int tw0 = wave * kWaveT;
+    if (has && tw0 < Tn) {  // uniform per wave
       const int64_t o = a.tbl_off[static_cast<int64_t>(lib) * (EDM_E_MAX + 1) + E];
-      const float *yt[1] = {ys + wave * m};
-      const bool ok[1] = {!(a.Ly_dev && a.Ly_dev[tgt[wave]] < Lx)};
-      float *const pred[1] = {nullptr};
-      Sums s[1];
-      wave_pairs<K, 1>(a.tbl_idx + o, a.tbl_w + o, m, yt, ok, pred, s);
-      if (a.rho && ok[0] && (threadIdx.x & (kWave - 1)) == 0)
-        a.rho[static_cast<int64_t>(lib) * a.ldrho + tgt[wave]] = pair_rho(m, s[0]);
+      const float *yt[kWaveT];
+      bool ok[kWaveT];
+      float *pred[kWaveT];
+#pragma unroll
+      for (int u = 0; u < kWaveT; ++u) {
+        const int t = tw0 + u;
+        yt[u] = ys + (t < Tn ? t : 0) * m;
+        ok[u] = t < Tn && !(a.Ly_dev && a.Ly_dev[tgt[t]] < Lx);
+        pred[u] = nullptr;
+      }
+      Sums s[kWaveT];
+      wave_pairs<K, kWaveT>(a.tbl_idx + o, a.tbl_w + o, m, yt, ok, pred, s);
+      if (a.rho && (threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+        for (int u = 0; u < kWaveT; ++u)
+          if (ok[u]) a.rho[static_cast<int64_t>(lib) * a.ldrho + tgt[tw0 + u]] = pair_rho(m, s[u]);
+      }
     }
   }
 }

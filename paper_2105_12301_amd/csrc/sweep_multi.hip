@@ -246,9 +246,7 @@ hipError_t launch_sweep_multi(const KnnArgs &a, int nslots, int64_t L_max, hipSt
   if (nslots <= 0) return hipSuccess;
   const unsigned gx = static_cast<unsigned>((L_max + kKnnThreads - 1) / kKnnThreads);
   const size_t shm = static_cast<size_t>(L_max) * sizeof(float);
-  // With the matrix-core filter, E >= kGramEMin runs in the filtered groups
-  // (their slot layout needs E_hi + |group| <= 16, or a shared first chunk).
-  constexpr int kGramGroups[][2] = {{9, 12}, {13, 14}, {15, 15}, {16, 18}, {19, 20}};
+  // With the matrix-core filter, E >= kGramEMin runs in the filtered groups.
   const bool gram = a.gram_nrm != nullptr && L_max <= kGramLMax;
   auto hi_of = [&](int lo, int top) {
     int hi = top < a.E_max ? top : a.E_max;

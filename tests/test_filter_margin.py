@@ -1,15 +1,17 @@
 """The matrix-core filter's margin, checked on the CPU.
 
-The chosen form skips a candidate when its BF16 estimate D of
-s N_E(q) - 2 G_E(p, q) exceeds T = kth - s N_E(p) (s = 1 - 2^-12).  That is
-safe iff, for every pair, D <= fl(K(p, q) - s N_E(p)) with K the exact float32
-key (a candidate whose key is below the k-th key then always passes).  This
-emulates the filter's arithmetic exactly where it is exact (BF16 splits, BF16
-products, the norms) and the FP32 accumulation of the matrix core in several
-summation orders, then checks that inequality for every pair of small series
-chosen to stress it.  The accumulation order inside the hardware is not
-specified, hence the several orders; the margin leaves a factor of three over
-the worst-case bound for any order.
+The chosen form evaluates, per (query p, candidate q), the BF16 product chain
+    e = s N_E(q) - 2 G_E(p, q) - T,   T = kth - s N_E(p) + 2^-90  (s = 1 - 2^-12)
+with -T carried as a BF16 pair rounded down (so the chain subtracts at least
+T) and skips q when e is not negative.  That is safe iff e < 0 whenever the
+exact float32 key K(p, q) is at most kth (such a candidate could enter the
+list).  This emulates the filter's arithmetic exactly where it is exact (BF16
+splits, BF16 products, the norms, the threshold pair) and the FP32
+accumulation of the matrix core in several summation orders, then checks the
+sign for every pair of small series chosen to stress it, with kth equal to
+the pair's own key (the tightest case) and larger.  The accumulation order
+inside the hardware is not specified, hence the several orders; the margin
+leaves a factor of three over the worst-case bound for any order.
 """
 import numpy as np
 import pytest
@@ -18,6 +20,7 @@ from paper_2105_12301_amd import synth
 
 S = np.float32(1.0 - 2.0 ** -12)
 FLOOR = np.float32(2.0 ** -90)
+BIG = np.float32(2.0 ** 120)
 
 
 def bf16(v):
@@ -25,6 +28,14 @@ def bf16(v):
     u = np.asarray(v, np.float32).view(np.uint32).astype(np.uint64)
     r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
     return r.astype(np.uint32).view(np.float32)
+
+
+def bf16_down(v):
+    """Round float32 to BF16 toward -inf, returned as float32."""
+    u = np.asarray(v, np.float32).view(np.uint32).astype(np.uint64)
+    t = u >> 16
+    t = np.where(((u >> 31) & 1).astype(bool) & ((u & 0xFFFF) != 0), t + 1, t)
+    return (t << 16).astype(np.uint32).view(np.float32)
 
 
 def split(v):
@@ -72,7 +83,16 @@ def accumulate(terms, order):
     return acc
 
 
-def filter_estimate(x, E, m, order):
+def threshold_terms(kth, vp, m):
+    """-T as the BF16 pair of the threshold slot, [q][p] broadcast."""
+    T = np.minimum(((kth - vp[None, :]).astype(np.float32) + FLOOR).astype(np.float32), BIG)
+    u = (-T).astype(np.float32)
+    hi = bf16(u)
+    lo = bf16_down((u - hi).astype(np.float32))
+    return [np.broadcast_to(hi, (m, m)).astype(np.float32), np.broadcast_to(lo, (m, m)).astype(np.float32)]
+
+
+def filter_estimate(x, E, m, order, kth=None):
     mu = np.float32(np.mean(x.astype(np.float64)))
     b = (x - mu).astype(np.float32)
     hi, lo = split(b)
@@ -86,8 +106,10 @@ def filter_estimate(x, E, m, order):
         terms.append((al[:, None] * bh[None, :]).astype(np.float32))
     terms.append(np.repeat(nqh[:, None], m, axis=1))
     terms.append(np.repeat(nql[:, None], m, axis=1))
-    D = accumulate(terms, order)
     vp = (nqh + nql).astype(np.float32)                # the query side's s N_E(p)
+    if kth is not None:                                # kth[q][p]
+        terms += threshold_terms(kth, vp, m)
+    D = accumulate(terms, order)
     return D, vp
 
 
@@ -111,11 +133,13 @@ def test_filter_never_drops_a_closer_candidate(E, order):
     for name, x in cases():
         m = len(x) - E + 1
         K = canonical_keys(x, E, m)                     # [p][q], symmetric
-        D, vp = filter_estimate(x, E, m, order)         # D[q][p]
-        T = ((K.T - vp[None, :]).astype(np.float32) + FLOOR).astype(np.float32)  # [q][p]
-        bad = ~(D <= T)
-        np.fill_diagonal(bad, False)
-        assert not bad.any(), (name, E, order, int(bad.sum()))
+        for scale in (1.0, 1.0 + 2.0 ** -20, 3.0, 1e6, np.inf):
+            kth = (np.full_like(K, np.inf) if np.isinf(scale)          # list not full yet
+                   else (K.T * np.float32(scale)).astype(np.float32))  # [q][p], >= the pair's key
+            e, _ = filter_estimate(x, E, m, order, kth)
+            bad = ~np.signbit(e)
+            np.fill_diagonal(bad, False)
+            assert not bad.any(), (name, E, order, scale, int(bad.sum()))
 
 
 def test_margin_is_tight_enough_to_filter():
@@ -127,7 +151,6 @@ def test_margin_is_tight_enough_to_filter():
     K = canonical_keys(x, E, m)
     np.fill_diagonal(K, np.inf)
     kth = np.sort(K, axis=1)[:, E]
-    D, vp = filter_estimate(x, E, m, "forward")
-    T = (kth - vp).astype(np.float32)
-    passed = (D <= T[None, :]).sum(axis=0)
+    e, _ = filter_estimate(x, E, m, "forward", np.broadcast_to(kth[None, :], (m, m)))
+    passed = np.signbit(e).sum(axis=0)
     assert np.median(passed) <= 2 * (E + 1)
