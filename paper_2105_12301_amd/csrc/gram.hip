@@ -296,23 +296,9 @@ __device__ __forceinline__ uint32_t tile_of(uint32_t code) {
   return (code & 15u) | ((code >> 4) & 0xf0u) | ((code >> 8) & 0xf00u);
 }
 
-// Insertion of a partner-list entry: lexicographic on (key, index) with the
-// index compared unsigned, so empty entries (index -1) sort last.
-template <int OFF, int K, int TOT>
-__device__ __forceinline__ void slice_insert_lex(float (&qk)[TOT], int (&qi)[TOT], float key, int q) {
-  const uint32_t uq = static_cast<uint32_t>(q);
-#pragma unroll
-  for (int i = K - 1; i > 0; --i) {
-    const bool lt_prev = key < qk[OFF + i - 1] ||
-                         (key == qk[OFF + i - 1] && uq < static_cast<uint32_t>(qi[OFF + i - 1]));
-    const bool lt_cur =
-        key < qk[OFF + i] || (key == qk[OFF + i] && uq < static_cast<uint32_t>(qi[OFF + i]));
-    qi[OFF + i] = lt_prev ? qi[OFF + i - 1] : (lt_cur ? q : qi[OFF + i]);
-    qk[OFF + i] = lt_prev ? qk[OFF + i - 1] : (lt_cur ? key : qk[OFF + i]);
-  }
-  const bool lt0 = key < qk[OFF] || (key == qk[OFF] && uq < static_cast<uint32_t>(qi[OFF]));
-  qi[OFF] = lt0 ? q : qi[OFF];
-  qk[OFF] = lt0 ? key : qk[OFF];
+// (key, index) order with the index compared unsigned (index -1 sorts last).
+__device__ __forceinline__ bool lex_less(float ka, int ia, float kb, int ib) {
+  return ka < kb || (ka == kb && static_cast<uint32_t>(ia) < static_cast<uint32_t>(ib));
 }
 
 // One workgroup's share of a filtered scan: query block `bx` of row `row`,
@@ -615,18 +601,58 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   flush();
 
   // Each query's two half-lists -> its full list (both lanes end equal).
+  // [own list ascending, maxima, partner list descending] is bitonic; its
+  // first half-cleaner stage (elementwise minimum) leaves the N smallest as a
+  // bitonic sequence, and the remaining stages sort it.  Blocks that start at
+  // or beyond K only order entries that are dropped, so they are skipped.
+  // Order: (key, index) lexicographic, the index unsigned (empty entries last).
   static_for<ELO, EHI>([&](auto EC) {
     constexpr int E = decltype(EC)::value;
+    constexpr int K = E + 1;
     constexpr int OFF = list_off<ELO>(E);
-    float pk[E + 1];
-    int pi[E + 1];
+    constexpr int N = K <= 16 ? 16 : 32;
+    static_assert(N - K < K, "every position of the lower half holds an entry");
+    float ck[N];
+    int ci[N];
 #pragma unroll
-    for (int i = 0; i < E + 1; ++i) {
-      pk[i] = __shfl_xor(qk[OFF + i], 32);
-      pi[i] = __shfl_xor(qi[OFF + i], 32);
+    for (int i = 0; i < N; ++i) {
+      const int j = N - 1 - i;  // partner entry facing position i, if j < K
+      float pk = 0.0f;
+      int pi = 0;
+      if (j < K) {
+        pk = __shfl_xor(qk[OFF + j], 32);
+        pi = __shfl_xor(qi[OFF + j], 32);
+      }
+      if (i < K && j < K) {
+        const bool lt = lex_less(pk, pi, qk[OFF + i], qi[OFF + i]);
+        ck[i] = lt ? pk : qk[OFF + i];
+        ci[i] = lt ? pi : qi[OFF + i];
+      } else if (i < K) {
+        ck[i] = qk[OFF + i];
+        ci[i] = qi[OFF + i];
+      } else {
+        ck[i] = pk;
+        ci[i] = pi;
+      }
     }
 #pragma unroll
-    for (int i = 0; i < E + 1; ++i) slice_insert_lex<OFF, E + 1, TOT>(qk, qi, pk[i], pi[i]);
+    for (int d = N / 2; d > 0; d >>= 1)
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+        if ((i & d) == 0 && (i & ~(2 * d - 1)) < K) {
+          const bool sw = lex_less(ck[i + d], ci[i + d], ck[i], ci[i]);
+          const float k0 = ck[i], k1 = ck[i + d];
+          const int i0 = ci[i], i1 = ci[i + d];
+          ck[i] = sw ? k1 : k0;
+          ci[i] = sw ? i1 : i0;
+          ck[i + d] = sw ? k0 : k1;
+          ci[i + d] = sw ? i0 : i1;
+        }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      qk[OFF + i] = ck[i];
+      qi[OFF + i] = ci[i];
+    }
   });
 
   // Epilogue: E alternates between the two lanes of a query.  The co-moments
