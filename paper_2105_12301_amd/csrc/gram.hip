@@ -301,6 +301,93 @@ __device__ __forceinline__ bool lex_less(float ka, int ia, float kb, int ib) {
   return ka < kb || (ka == kb && static_cast<uint32_t>(ia) < static_cast<uint32_t>(ib));
 }
 
+// Final step (Section 2.1 step 3) for dimension E of query p, E one of E0
+// and E1 = E0 + 1 (or E0 alone when E1 == E0): the same float64 arithmetic,
+// in the same order, as finish_list, with the lag and neighbour counts set
+// at run time so that the two lane halves finish two dimensions at once.
+// idx: the sorted list (E + 1 entries used).
+template <int E0, int E1, int NV>
+__device__ __forceinline__ Mom finish_round(const KnnArgs &a, int row, int p, int L, int Tp,
+                                            uint32_t need, const float (&vp)[NV],
+                                            const int (&idx)[E1 + 1], int E,
+                                            const float *__restrict__ xs) {
+  constexpr int KM = E1 + 1;
+  const bool hi = E != E0;
+  const int K = E + 1;
+  const int mE = L - (E - 1) - Tp;
+  Mom mine = mom_zero();
+  const bool want_table = a.mom == nullptr && ((need >> (E - 1)) & 1u);
+  if (p < mE && mE - 1 >= K && (a.mom != nullptr || want_table)) {
+    int q[KM];
+    double D[KM];
+    double dmin = __builtin_inf();
+#pragma unroll
+    for (int r = 0; r < KM; ++r) {
+      q[r] = idx[r] < 0 ? 0 : idx[r];
+      double s2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < E1; ++j) {
+        if (j < E0 || hi) {
+          const double d = static_cast<double>(vp[j]) - static_cast<double>(xs[q[r] + j]);
+          s2 += d * d;
+        }
+      }
+      D[r] = sqrt(s2);
+      if (r < KM - 1 || hi || E1 == E0) dmin = fmin(dmin, D[r]);
+    }
+    double wsum = 0.0;
+#pragma unroll
+    for (int r = 0; r < KM; ++r) {
+      const double d = D[r];
+      const double wq = dmin > 0.0 ? exp(-d / dmin) : (d == 0.0 ? 1.0 : 0.0);
+      if (r < KM - 1 || hi || E1 == E0) wsum += wq;
+      D[r] = wq;
+    }
+    const double inv = 1.0 / wsum;
+    if (want_table) {
+      int32_t *ti;
+      float *tw;
+      int64_t base;
+      if (a.tbl_off) {
+        const int64_t o = a.tbl_off[static_cast<int64_t>(row) * (EDM_E_MAX + 1) + E];
+        ti = a.tbl_idx + o;
+        tw = a.tbl_w + o;
+        base = static_cast<int64_t>(p) * K;
+      } else {
+        ti = hi ? a.idxE[E1] : a.idxE[E0];
+        tw = hi ? a.wE[E1] : a.wE[E0];
+        base = static_cast<int64_t>(row) * (hi ? a.strideE[E1] : a.strideE[E0]) +
+               static_cast<int64_t>(p) * K;
+      }
+#pragma unroll
+      for (int i = 0; i < KM; ++i) {
+        if (i < KM - 1 || hi || E1 == E0) {
+          ti[base + i] = q[i];
+          tw[base + i] = static_cast<float>(D[i] * inv);
+        }
+      }
+    } else {
+      int32_t *keep = hi ? a.keepE[E1] : a.keepE[E0];
+      if (keep) {  // sweep mode: keep the sorted list for a later cross map
+        int32_t *kp = keep + static_cast<int64_t>(row) * (hi ? a.keep_strideE[E1] : a.keep_strideE[E0]) +
+                      static_cast<int64_t>(p) * K;
+#pragma unroll
+        for (int i = 0; i < KM; ++i)
+          if (i < KM - 1 || hi || E1 == E0) kp[i] = q[i];
+      }
+      const int o_off = (E - 1) + Tp;
+      double yh = 0.0;
+#pragma unroll
+      for (int i = 0; i < KM; ++i)
+        if (i < KM - 1 || hi || E1 == E0) yh += (D[i] * inv) * static_cast<double>(xs[q[i] + o_off]);
+      mine.n = 1.0;
+      mine.mo = static_cast<double>(xs[p + o_off]);
+      mine.mp = yh;
+    }
+  }
+  return mine;
+}
+
 // One workgroup's share of a filtered scan: query block `bx` of row `row`,
 // every E in [ELO, EHI].  Same outputs as the exact group scan.
 template <int ELO, int EHI>
@@ -659,16 +746,25 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   // are merged in the order of the exact scan (a 32-lane butterfly per half,
   // then the two halves of each 64-query group, then the groups in order), so
   // the correlations match it bit for bit.
-  static_for<ELO, EHI>([&](auto EC) {
-    constexpr int E = decltype(EC)::value;
-    constexpr int g = E - ELO;
-    const bool own = h1 == ((g & 1) != 0);
+  // Round r: the lower half finishes E = ELO + 2r, the upper half ELO + 2r + 1.
+  static_for<0, (NG - 1) / 2>([&](auto RC) {
+    constexpr int E0 = ELO + 2 * decltype(RC)::value;
+    constexpr int E1 = E0 + 1 <= EHI ? E0 + 1 : E0;
+    constexpr int K1 = E1 + 1;
+    const bool up = h1 && E1 != E0;
+    int idx[K1];
+#pragma unroll
+    for (int i = 0; i < K1; ++i) {
+      const int lo_i = i < E0 + 1 ? qi[list_off<ELO>(E0) + i] : -1;
+      idx[i] = up ? qi[list_off<ELO>(E1) + i] : lo_i;
+    }
     Mom mine = mom_zero();
-    if (own) mine = finish_list<E, list_off<ELO>(E), TOT, EHI>(a, row, p, L, Tp, need, vp, qi, xs);
+    if (!h1 || up) mine = finish_round<E0, E1, EHI>(a, row, p, L, Tp, need, vp, idx, up ? E1 : E0, xs);
     if (a.mom) {  // uniform
 #pragma unroll
       for (int m = 1; m < 32; m <<= 1) mine = mom_merge(mine, mom_shfl_xor(mine, m));
-      if (lane == ((g & 1) ? 32 : 0)) wmom[wave][g] = mine;
+      if (lane == 0) wmom[wave][E0 - ELO] = mine;
+      if (E1 != E0 && lane == 32) wmom[wave][E1 - ELO] = mine;
     }
   });
   if (a.mom == nullptr) return;
