@@ -79,7 +79,6 @@ constexpr float kGramFloor = 0x1p-90f;          // absolute slack: flushed tiny 
 constexpr float kGramSafeMax = 0x1p56f;         // larger |x - mu| switches the filter off
 constexpr int kQueueCap = 16;                   // queued tile masks per lane before a re-rank
 constexpr float kGramBig = 0x1p120f;            // |threshold| cap: finite BF16 operands
-constexpr int kPass1Step = 2;                   // pass 1 looks at every kPass1Step-th tile
 
 __device__ __forceinline__ uint32_t bf16_bits(float f) {  // round to nearest even (finite f)
   const uint32_t u = __float_as_uint(f);
@@ -110,6 +109,13 @@ __device__ __forceinline__ void read_window(const uint32_t *__restrict__ w32, in
   for (int i = 0; i < 5; ++i) W[i] = w32[w0 + i];
 #pragma unroll
   for (int i = 0; i < 4; ++i) out[i] = __builtin_amdgcn_alignbit(W[i + 1], W[i], sh);
+}
+
+// Minimum of two finite floats, one instruction (no NaN canonicalisation).
+__device__ __forceinline__ float vmin(float a, float b) {
+  float r;
+  asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
 }
 
 // Ascending bitonic sort of 32 values held in registers.
@@ -449,20 +455,12 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
 #pragma unroll
   for (int j = 0; j < EHI; ++j) vp[j] = qry ? xs[p + j] : 0.0f;
 
-  float qk[TOT];
-  int qi[TOT];
+  // Lists of E that are not needed (or whose range ends before p) stay idle.
+  auto list_active = [&](int E) {
+    return p < L - (E - 1) - Tp && (a.mom != nullptr || ((need >> (E - 1)) & 1u));
+  };
   bool act_any = false;
-  static_for<ELO, EHI>([&](auto EC) {
-    constexpr int E = decltype(EC)::value;
-    constexpr int OFF = list_off<ELO>(E);
-    const bool act = p < L - (E - 1) - Tp && (a.mom != nullptr || ((need >> (E - 1)) & 1u));
-    act_any = act_any || act;
-#pragma unroll
-    for (int i = 0; i < E + 1; ++i) {
-      qk[OFF + i] = act ? __builtin_inff() : -1.0f;
-      qi[OFF + i] = -1;
-    }
-  });
+  static_for<ELO, EHI>([&](auto EC) { act_any = act_any || list_active(decltype(EC)::value); });
 
   // Query norms s N_E(p); T_E = kth_E - s N_E(p) rides in the threshold slot.
   float nq[NG];
@@ -503,27 +501,23 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
 #pragma unroll
     for (int g = 0; g < NG; ++g) nr_next[g] = nrm[g * ld + c0 + n];
   };
-  // HI_ONLY (pass 1) builds just the hi operands and the hi*hi product.
-  auto load_tile = [&](int c0, int c_next, auto hi_only) {
-    constexpr bool HI_ONLY = decltype(hi_only)::value;
+  auto load_tile = [&](int c0, int c_next) {
     const int qa = c0 + n;
 #pragma unroll
     for (int g = 0; g < NG; ++g) nr[g] = nr_next[g];
     fetch(c_next < m_lo ? c_next : c0);  // in bounds: c0 < m_lo and gram_ld >= L + 64
     static_for<0, NCH - 1>([&](auto CC) {
       constexpr int C = decltype(CC)::value;
-      uint32_t wh[4], wl[4] = {0u, 0u, 0u, 0u};
+      uint32_t wh[4], wl[4];
       read_window(xh32, qa + Lay::first_lag(C) + (h1 ? 8 : 0), wh);
-      if constexpr (!HI_ONLY) read_window(xl32, qa + Lay::first_lag(C) + (h1 ? 8 : 0), wl);
+      read_window(xl32, qa + Lay::first_lag(C) + (h1 ? 8 : 0), wl);
       build_a<Lay, C>(ah[C], al[C], wh, wl, nr, h1);
     });
     acc_s = f32x16_t{};
     if constexpr (Lay::kShared) {
       acc_s = mfma(ah[0], bsh, acc_s);
-      if constexpr (!HI_ONLY) {
-        acc_s = mfma(ah[0], bsl, acc_s);
-        acc_s = mfma(al[0], bsh, acc_s);
-      }
+      acc_s = mfma(ah[0], bsl, acc_s);
+      acc_s = mfma(al[0], bsh, acc_s);
     }
   };
   auto estimate = [&](int g) {
@@ -534,14 +528,6 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
       acc = mfma(ah[C], bl[g][C - C0], acc);
       acc = mfma(al[C], bh[g][C - C0], acc);
     }
-    return acc;
-  };
-  // Pass-1 estimate at E_hi from the hi halves only (one product per chunk):
-  // it only ranks candidates; the bound it leads to uses exact keys.
-  auto estimate_hi = [&]() {
-    f32x16_t acc = acc_s;
-#pragma unroll
-    for (int C = C0; C < NCH; ++C) acc = mfma(ah[C], bh[NG - 1][C - C0], acc);
     return acc;
   };
   // Exact float32 keys of candidate q for every E of the group (Algorithm 1,
@@ -560,7 +546,8 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   };
 
   // Pass 1 (estimates only): lane v-slot b keeps the candidate with the
-  // smallest estimate at E_hi among candidates 32t + m(b); the 32 winners of
+  // smallest estimate at E_hi (hi halves only, one product per chunk) among
+  // candidates 64t + m(b); the 32 winners of
   // a query (16 per lane) are distinct candidates, so the K-th smallest of
   // their exact keys bounds the query's final K-th key from above, for every
   // E of the group.  These bounds cap the thresholds of pass 2 from the start.
@@ -568,31 +555,69 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
 #pragma unroll
   for (int g = 0; g < NG; ++g) ub[g] = __builtin_inff();
   if (pw < m_lo) {
+    // The tile index replaces the 9 low mantissa bits of the estimate (a
+    // relative change below 2^-14: the ranking only picks candidates), so one
+    // minimum keeps the estimate and its tile.  The estimates are finite.
+    static_assert(kGramLMax / 32 <= 0x1ff, "tile index field");
     float bm[16];
-    int bt[16];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      bm[v] = __builtin_inff();
-      bt[v] = -1;
-    }
-    fetch(0);
+    for (int v = 0; v < 16; ++v) bm[v] = __builtin_inff();
+    // Every second tile (candidates 64s + m(b)), two tiles per step so that
+    // independent product chains overlap their latency.  A second tile past
+    // the end repeats the first (same minimum).
+    auto hi_tile = [&](int c0, const uint32_t (&nrv)[NG]) {
+      uint32_t a_h[NCH][4];
+      static_for<0, NCH - 1>([&](auto CC) {
+        constexpr int C = decltype(CC)::value;
+        uint32_t wh[4], al_unused[4];
+        const uint32_t zero[4] = {0u, 0u, 0u, 0u};
+        read_window(xh32, c0 + n + Lay::first_lag(C) + (h1 ? 8 : 0), wh);
+        build_a<Lay, C>(a_h[C], al_unused, wh, zero, nrv, h1);
+      });
+      f32x16_t acc = {};
+      if constexpr (Lay::kShared) acc = mfma(a_h[0], bsh, acc);
+#pragma unroll
+      for (int C = C0; C < NCH; ++C) acc = mfma(a_h[C], bh[NG - 1][C - C0], acc);
+      return acc;
+    };
+    uint32_t nA[NG], nB[NG];
+    auto fetch2 = [&](int c0) {  // in bounds: c0 < m_lo + 64 <= gram_ld
+      const int cb = c0 + 64 < m_lo ? c0 + 64 : c0;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        nA[g] = nrm[g * ld + c0 + n];
+        nB[g] = nrm[g * ld + cb + n];
+      }
+    };
+    fetch2(0);
 #pragma unroll 1
-    for (int c0 = 0; c0 < m_lo; c0 += 32 * kPass1Step) {
-      load_tile(c0, c0 + 32 * kPass1Step, std::true_type{});
-      const f32x16_t acc = estimate_hi();
+    for (int c0 = 0; c0 < m_lo; c0 += 128) {
+      const int cb = c0 + 64 < m_lo ? c0 + 64 : c0;
+      uint32_t na[NG], nb[NG];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        na[g] = nA[g];
+        nb[g] = nB[g];
+      }
+      if (c0 + 128 < m_lo) fetch2(c0 + 128);
+      const f32x16_t accA = hi_tile(c0, na);
+      const f32x16_t accB = hi_tile(cb, nb);
+      const uint32_t tA = static_cast<uint32_t>(c0) >> 5, tB = static_cast<uint32_t>(cb) >> 5;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const bool lt = acc[v] < bm[v];
-        bm[v] = lt ? acc[v] : bm[v];
-        bt[v] = lt ? c0 : bt[v];
+        const float eA = __uint_as_float((__float_as_uint(accA[v]) & ~0x1ffu) | tA);
+        const float eB = __uint_as_float((__float_as_uint(accB[v]) & ~0x1ffu) | tB);
+        bm[v] = vmin(bm[v], vmin(eA, eB));
       }
     }
     float kb[NG][16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int q = bt[v] + 8 * (v >> 2) + (h1 ? 4 : 0) + (v & 3);
+      const bool won = bm[v] != __builtin_inff();
+      const int bt = won ? static_cast<int>(__float_as_uint(bm[v]) & 0x1ffu) * 32 : -1;
+      const int q = bt + 8 * (v >> 2) + (h1 ? 4 : 0) + (v & 3);
       float key[NG];
-      exact_keys(bt[v] < 0 ? 0 : q, bt[v] >= 0 && q != p, key);
+      exact_keys(bt < 0 ? 0 : q, bt >= 0 && q != p, key);
 #pragma unroll
       for (int g = 0; g < NG; ++g) kb[g][v] = key[g];
     }
@@ -608,6 +633,19 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
       ub[E - ELO] = a[E];  // K-th smallest, K = E + 1
     });
   }
+
+  float qk[TOT];
+  int qi[TOT];
+  static_for<ELO, EHI>([&](auto EC) {
+    constexpr int E = decltype(EC)::value;
+    constexpr int OFF = list_off<ELO>(E);
+    const bool act = list_active(E);
+#pragma unroll
+    for (int i = 0; i < E + 1; ++i) {
+      qk[OFF + i] = act ? __builtin_inff() : -1.0f;
+      qi[OFF + i] = -1;
+    }
+  });
 
   // Pass 2: every E's threshold rides in the products, so the estimate of
   // E is D - T and a candidate survives where the minimum over the group's E
@@ -668,7 +706,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     const bool pass_all = unsafe && act_any;  // filter off: every candidate is re-ranked
 #pragma unroll 1
     for (int c0 = 0; c0 < m_lo; c0 += 32) {
-      load_tile(c0, c0 + 32, std::false_type{});
+      load_tile(c0, c0 + 32);
       // Only the sign of the minimum over E matters: OR of the sign bits.
       uint32_t e[16];
       static_for<0, NG - 1>([&](auto GC) {
