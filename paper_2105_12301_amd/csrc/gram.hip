@@ -501,18 +501,37 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
 #pragma unroll
     for (int g = 0; g < NG; ++g) nr_next[g] = nrm[g * ld + c0 + n];
   };
-  auto load_tile = [&](int c0, int c_next) {
-    const int qa = c0 + n;
-#pragma unroll
-    for (int g = 0; g < NG; ++g) nr[g] = nr_next[g];
-    fetch(c_next < m_lo ? c_next : c0);  // in bounds: c0 < m_lo and gram_ld >= L + 64
+  // The LDS words of the next tile's windows are read one tile ahead as
+  // well (rh, rl: five words per window; the funnel shift comes at use).
+  uint32_t rh[NCH][5], rl[NCH][5];
+  auto read_raw = [&](int c0) {
     static_for<0, NCH - 1>([&](auto CC) {
       constexpr int C = decltype(CC)::value;
+      const int w0 = (c0 + n + Lay::first_lag(C) + (h1 ? 8 : 0)) >> 1;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        rh[C][i] = xh32[w0 + i];
+        rl[C][i] = xl32[w0 + i];
+      }
+    });
+  };
+  auto load_tile = [&](int c0, int c_next) {
+    const int cn = c_next < m_lo ? c_next : c0;  // in bounds: c0 < m_lo and gram_ld >= L + 64
+#pragma unroll
+    for (int g = 0; g < NG; ++g) nr[g] = nr_next[g];
+    fetch(cn);
+    static_for<0, NCH - 1>([&](auto CC) {
+      constexpr int C = decltype(CC)::value;
+      const uint32_t sh = static_cast<uint32_t>((n + Lay::first_lag(C)) & 1) * 16u;  // c0 is even
       uint32_t wh[4], wl[4];
-      read_window(xh32, qa + Lay::first_lag(C) + (h1 ? 8 : 0), wh);
-      read_window(xl32, qa + Lay::first_lag(C) + (h1 ? 8 : 0), wl);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        wh[i] = __builtin_amdgcn_alignbit(rh[C][i + 1], rh[C][i], sh);
+        wl[i] = __builtin_amdgcn_alignbit(rl[C][i + 1], rl[C][i], sh);
+      }
       build_a<Lay, C>(ah[C], al[C], wh, wl, nr, h1);
     });
+    read_raw(cn);
     acc_s = f32x16_t{};
     if constexpr (Lay::kShared) {
       acc_s = mfma(ah[0], bsh, acc_s);
@@ -703,6 +722,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   refresh();
   if (pw < m_lo) {
     fetch(0);
+    read_raw(0);
     const bool pass_all = unsafe && act_any;  // filter off: every candidate is re-ranked
 #pragma unroll 1
     for (int c0 = 0; c0 < m_lo; c0 += 32) {
