@@ -311,11 +311,10 @@ __device__ __forceinline__ bool lex_less(float ka, int ia, float kb, int ib) {
 // and E1 = E0 + 1 (or E0 alone when E1 == E0): the same float64 arithmetic,
 // in the same order, as finish_list, with the lag and neighbour counts set
 // at run time so that the two lane halves finish two dimensions at once.
-// idx: the sorted list (E + 1 entries used).
-template <int E0, int E1, int NV>
+// idx: the sorted list (E + 1 entries used); the query's samples come from xs.
+template <int E0, int E1>
 __device__ __forceinline__ Mom finish_round(const KnnArgs &a, int row, int p, int L, int Tp,
-                                            uint32_t need, const float (&vp)[NV],
-                                            const int (&idx)[E1 + 1], int E,
+                                            uint32_t need, const int (&idx)[E1 + 1], int E,
                                             const float *__restrict__ xs) {
   constexpr int KM = E1 + 1;
   const bool hi = E != E0;
@@ -334,7 +333,7 @@ __device__ __forceinline__ Mom finish_round(const KnnArgs &a, int row, int p, in
 #pragma unroll
       for (int j = 0; j < E1; ++j) {
         if (j < E0 || hi) {
-          const double d = static_cast<double>(vp[j]) - static_cast<double>(xs[q[r] + j]);
+          const double d = static_cast<double>(xs[p + j]) - static_cast<double>(xs[q[r] + j]);
           s2 += d * d;
         }
       }
@@ -451,9 +450,6 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   const bool qry = p < m_lo;
   const int pc = qry ? p : 0;
 
-  float vp[EHI];
-#pragma unroll
-  for (int j = 0; j < EHI; ++j) vp[j] = qry ? xs[p + j] : 0.0f;
 
   // Lists of E that are not needed (or whose range ends before p) stay idle.
   auto list_active = [&](int E) {
@@ -555,7 +551,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     float acc = 0.0f;
     static_for<0, EHI - 1>([&](auto JC) {
       constexpr int j = decltype(JC)::value;
-      const float d = vp[j] - xs[q + j];
+      const float d = xs[pc + j] - xs[q + j];
       acc = acc + d * d;
       if constexpr (j + 1 >= ELO) {
         constexpr int E = j + 1;
@@ -678,8 +674,15 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     static_for<ELO, EHI>([&](auto EC) {
       constexpr int E = decltype(EC)::value;
       constexpr int g = E - ELO;
-      const float own = qk[list_off<ELO>(E) + E];
-      const float kth = fminf(fminf(own, __shfl_xor(own, 32)), ub[g]);
+      constexpr int OFF = list_off<ELO>(E);
+      const float own = qk[OFF + E];
+      // K-th smallest key of the query's two half-lists together: the largest
+      // elementwise minimum of one sorted list against the other reversed.
+      float kth = ub[g];
+      float u = -__builtin_inff();
+#pragma unroll
+      for (int i = 0; i <= E; ++i) u = fmaxf(u, fminf(qk[OFF + i], __shfl_xor(qk[OFF + E - i], 32)));
+      kth = fminf(kth, u);
       const float T = own < 0.0f ? -kGramBig : fminf((kth - nq[g]) + kGramFloor, kGramBig);
       set_threshold<Lay>(bh[g][NCH - 1 - C0], bl[g][NCH - 1 - C0], T, h1);
     });
@@ -724,23 +727,35 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     fetch(0);
     read_raw(0);
     const bool pass_all = unsafe && act_any;  // filter off: every candidate is re-ranked
-#pragma unroll 1
-    for (int c0 = 0; c0 < m_lo; c0 += 32) {
-      load_tile(c0, c0 + 32);
-      // Only the sign of the minimum over E matters: OR of the sign bits.
-      uint32_t e[16];
+    // Only the sign of the minimum over E matters: OR of the sign bits.
+    auto estimates = [&](uint32_t (&e)[16]) {
       static_for<0, NG - 1>([&](auto GC) {
         constexpr int g = decltype(GC)::value;
         const f32x16_t acc = estimate(g);
 #pragma unroll
         for (int v = 0; v < 16; ++v) e[v] = (g == 0 ? 0u : e[v]) | __float_as_uint(acc[v]);
       });
+    };
+    // The next tile's products are issued before this tile's survivors are
+    // queued, so the two overlap.  Products issued before a re-rank use the
+    // older (larger) thresholds: more survivors, never fewer.
+    uint32_t e[16];
+    load_tile(0, 32);
+    estimates(e);
+#pragma unroll 1
+    for (int c0 = 0; c0 < m_lo; c0 += 32) {
+      const int cn = c0 + 32 < m_lo ? c0 + 32 : c0;  // the last step repeats a tile, unused
+      uint32_t e_next[16];
+      load_tile(cn, cn + 32);
+      estimates(e_next);
       uint32_t bits = sign_mask(e);
       if (unsafe) bits = pass_all ? kSignBits : 0u;
       qbuf[cnt * kWave] = bits | tile_code(static_cast<uint32_t>(c0) >> 5);
       cnt += bits != 0u;
       nsv += __builtin_popcount(bits);
       if (__builtin_amdgcn_ballot_w64(cnt == kQueueCap)) flush();
+#pragma unroll
+      for (int v = 0; v < 16; ++v) e[v] = e_next[v];
     }
   }
   flush();
@@ -817,7 +832,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
       idx[i] = up ? qi[list_off<ELO>(E1) + i] : lo_i;
     }
     Mom mine = mom_zero();
-    if (!h1 || up) mine = finish_round<E0, E1, EHI>(a, row, p, L, Tp, need, vp, idx, up ? E1 : E0, xs);
+    if (!h1 || up) mine = finish_round<E0, E1>(a, row, p, L, Tp, need, idx, up ? E1 : E0, xs);
     if (a.mom) {  // uniform
 #pragma unroll
       for (int m = 1; m < 32; m <<= 1) mine = mom_merge(mine, mom_shfl_xor(mine, m));
