@@ -77,6 +77,7 @@ static_assert(kGramWaves * 32 == kKnnThreads, "a workgroup covers one query bloc
 constexpr float kGramScale = 1.0f - 0x1p-12f;  // s = 1 - 2^-12
 constexpr float kGramFloor = 0x1p-90f;          // absolute slack: flushed tiny products
 constexpr float kGramSafeMax = 0x1p56f;         // larger |x - mu| switches the filter off
+constexpr int kPass1Gap = 8 * 32;               // pass 1 samples one tile in eight
 constexpr int kQueueCap = 16;                   // queued tile masks per lane before a re-rank
 constexpr float kGramBig = 0x1p120f;            // |threshold| cap: finite BF16 operands
 
@@ -562,7 +563,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
 
   // Pass 1 (estimates only): lane v-slot b keeps the candidate with the
   // smallest estimate at E_hi (hi halves only, one product per chunk) among
-  // candidates 64t + m(b); the 32 winners of
+  // the sampled candidates kPass1Gap t + m(b); the 32 winners of
   // a query (16 per lane) are distinct candidates, so the K-th smallest of
   // their exact keys bounds the query's final K-th key from above, for every
   // E of the group.  These bounds cap the thresholds of pass 2 from the start.
@@ -577,9 +578,9 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     float bm[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) bm[v] = __builtin_inff();
-    // Every second tile (candidates 64s + m(b)), two tiles per step so that
-    // independent product chains overlap their latency.  A second tile past
-    // the end repeats the first (same minimum).
+    // Every eighth tile (candidates kPass1Gap s + m(b)), two tiles per step
+    // so that independent product chains overlap their latency.  A second
+    // tile past the end repeats the first (same minimum).
     auto hi_tile = [&](int c0, const uint32_t (&nrv)[NG]) {
       uint32_t a_h[NCH][4];
       static_for<0, NCH - 1>([&](auto CC) {
@@ -597,7 +598,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     };
     uint32_t nA[NG], nB[NG];
     auto fetch2 = [&](int c0) {  // in bounds: c0 < m_lo + 64 <= gram_ld
-      const int cb = c0 + 64 < m_lo ? c0 + 64 : c0;
+      const int cb = c0 + kPass1Gap < m_lo ? c0 + kPass1Gap : c0;
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
         nA[g] = nrm[g * ld + c0 + n];
@@ -606,15 +607,15 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     };
     fetch2(0);
 #pragma unroll 1
-    for (int c0 = 0; c0 < m_lo; c0 += 128) {
-      const int cb = c0 + 64 < m_lo ? c0 + 64 : c0;
+    for (int c0 = 0; c0 < m_lo; c0 += 2 * kPass1Gap) {
+      const int cb = c0 + kPass1Gap < m_lo ? c0 + kPass1Gap : c0;
       uint32_t na[NG], nb[NG];
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
         na[g] = nA[g];
         nb[g] = nB[g];
       }
-      if (c0 + 128 < m_lo) fetch2(c0 + 128);
+      if (c0 + 2 * kPass1Gap < m_lo) fetch2(c0 + 2 * kPass1Gap);
       const f32x16_t accA = hi_tile(c0, na);
       const f32x16_t accB = hi_tile(cb, nb);
       const uint32_t tA = static_cast<uint32_t>(c0) >> 5, tB = static_cast<uint32_t>(cb) >> 5;
