@@ -560,6 +560,23 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
       }
     });
   };
+  // The same for two candidates at once (two independent sums).
+  auto exact_keys2 = [&](int q0, bool ok0, float (&k0)[NG], int q1, bool ok1, float (&k1)[NG]) {
+    float a0 = 0.0f, a1 = 0.0f;
+    static_for<0, EHI - 1>([&](auto JC) {
+      constexpr int j = decltype(JC)::value;
+      const float xp = xs[pc + j];
+      const float d0 = xp - xs[q0 + j];
+      const float d1 = xp - xs[q1 + j];
+      a0 = a0 + d0 * d0;
+      a1 = a1 + d1 * d1;
+      if constexpr (j + 1 >= ELO) {
+        constexpr int E = j + 1;
+        k0[E - ELO] = (ok0 && q0 < L - (E - 1) - Tp) ? a0 : __builtin_inff();
+        k1[E - ELO] = (ok1 && q1 < L - (E - 1) - Tp) ? a1 : __builtin_inff();
+      }
+    });
+  };
 
   // Pass 1 (estimates only): lane v-slot b keeps the candidate with the
   // smallest estimate at E_hi (hi halves only, one product per chunk) among
@@ -690,14 +707,16 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   };
   // Re-rank the queued candidates, lowest first: uniform trip count and a
   // branch-free body keep the lists in place in registers.
+  // Two survivors per step (where the register budget allows): their key
+  // chains are independent and overlap; they are inserted in order, so each
+  // list still sees ascending q.
+  constexpr int kStep = TOT <= 44 ? 2 : 1;
   auto flush = [&]() {
-    const int n_iter = wave_max(nsv);
+    const int n_iter = (wave_max(nsv) + kStep - 1) / kStep;
     int j = 0;
     uint32_t cur = qbuf[0];
     uint32_t nxt = qbuf[kWave];
-#pragma unroll 1
-    for (int it = 0; it < n_iter; ++it) {
-      const bool has = it < nsv;
+    auto take = [&](bool has) {  // this lane's next survivor (0 when none is left)
       const bool adv = (cur & kSignBits) == 0u;  // entry done: the next one holds the next survivor
       cur = adv ? nxt : cur;
       j += adv ? 1 : 0;
@@ -706,18 +725,40 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
       const int pos = bit ? __builtin_ctz(bit) : 0;
       cur ^= bit ? (1u << pos) : 0u;
       const int qq = static_cast<int>(tile_of(cur)) * 32 + (pos & ~7) + (pos & 3) + (h1 ? 4 : 0);
-      const int q = has ? qq : 0;
-      float key[NG];
-      exact_keys(q, has && q != p, key);
-      static_for<ELO, EHI>([&](auto EC) {
-        constexpr int E = decltype(EC)::value;
-        // The empty asm hides the +inf of idle lanes from the optimiser,
-        // which would otherwise branch around the insertion.
-        float kin = key[E - ELO];
-        asm volatile("" : "+v"(kin));
-        if (__builtin_amdgcn_ballot_w64(kin < qk[list_off<ELO>(E) + E]))
-          slice_insert<list_off<ELO>(E), E + 1, TOT>(qk, qi, kin, q);
-      });
+      return has ? qq : 0;
+    };
+#pragma unroll 1
+    for (int it = 0; it < n_iter; ++it) {
+      if constexpr (kStep == 2) {
+        const bool has0 = 2 * it < nsv, has1 = 2 * it + 1 < nsv;
+        const int q0 = take(has0);
+        const int q1 = take(has1);
+        float key0[NG], key1[NG];
+        exact_keys2(q0, has0 && q0 != p, key0, q1, has1 && q1 != p, key1);
+        static_for<ELO, EHI>([&](auto EC) {
+          constexpr int E = decltype(EC)::value;
+          // The empty asm hides the +inf of idle lanes from the optimiser,
+          // which would otherwise branch around the insertion.
+          float kin0 = key0[E - ELO], kin1 = key1[E - ELO];
+          asm volatile("" : "+v"(kin0), "+v"(kin1));
+          if (__builtin_amdgcn_ballot_w64(kin0 < qk[list_off<ELO>(E) + E]))
+            slice_insert<list_off<ELO>(E), E + 1, TOT>(qk, qi, kin0, q0);
+          if (__builtin_amdgcn_ballot_w64(kin1 < qk[list_off<ELO>(E) + E]))
+            slice_insert<list_off<ELO>(E), E + 1, TOT>(qk, qi, kin1, q1);
+        });
+      } else {
+        const bool has = it < nsv;
+        const int q = take(has);
+        float key[NG];
+        exact_keys(q, has && q != p, key);
+        static_for<ELO, EHI>([&](auto EC) {
+          constexpr int E = decltype(EC)::value;
+          float kin = key[E - ELO];
+          asm volatile("" : "+v"(kin));
+          if (__builtin_amdgcn_ballot_w64(kin < qk[list_off<ELO>(E) + E]))
+            slice_insert<list_off<ELO>(E), E + 1, TOT>(qk, qi, kin, q);
+        });
+      }
     }
     cnt = 0;
     nsv = 0;
