@@ -59,7 +59,7 @@ typedef struct edm_ctx edm_ctx;
  *                   candidate scan per group of E values, extending one
  *                   running key (the key for E is the key for E-1 plus one
  *                   rounded term).
- * EDM_FORM_CHOSEN : EDM_FORM_BATCHED, and for E >= 9 (series up to 14336
+ * EDM_FORM_CHOSEN : EDM_FORM_BATCHED, and for E >= 5 (series up to 14336
  *                   samples) a BF16 matrix-core estimate of every key filters
  *                   the candidates; the ones that may enter a top-k list are
  *                   re-ranked with the exact float32 key.
@@ -120,7 +120,7 @@ int edm_embed(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau,
  *        step 3; when min d = 0 the weights are 1 at zero distance and 0
  *        elsewhere before normalising                               (or NULL)
  * nq = L - (E-1)*tau - Tp.
- * In EDM_FORM_CHOSEN with tau = 1, k = E+1, E >= 9, L <= 14336 and dist ==
+ * In EDM_FORM_CHOSEN with tau = 1, k = E+1, E >= 5, L <= 14336 and dist ==
  * NULL, the table comes from the matrix-core filtered scan (same result). */
 int edm_knn(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau,
             int32_t Tp, int32_t k, int32_t *idx, float *dist, float *w);

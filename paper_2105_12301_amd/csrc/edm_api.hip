@@ -302,7 +302,7 @@ int edm_simplex_sweep(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N,
   EDM_RC(upload(ctx, L, sizeof(int64_t) * N, L_dev));
   if (batched) {
     // Batched form: one candidate scan per group of E values (through the
-    // matrix-core filter for E >= 9 in the chosen form).
+    // matrix-core filter for E >= 5 in the chosen form).
     const int64_t step = gram ? g_batch : N;
     for (int64_t b0 = 0; b0 < N; b0 += step) {
       const int64_t nb = std::min<int64_t>(step, N - b0);

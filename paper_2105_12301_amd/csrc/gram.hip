@@ -1,4 +1,4 @@
-// Chosen form of the distance step for E >= 9: a BF16 matrix-core Gram
+// Chosen form of the distance step for E >= 5: a BF16 matrix-core Gram
 // filter with an exact re-rank (kEDM paper: Section 2.1 steps 1-4 and
 // Algorithms 1-2 define what is computed; the filter is this library's own
 // design for gfx950).
@@ -812,7 +812,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     constexpr int E = decltype(EC)::value;
     constexpr int K = E + 1;
     constexpr int OFF = list_off<ELO>(E);
-    constexpr int N = K <= 16 ? 16 : 32;
+    constexpr int N = K <= 8 ? 8 : (K <= 16 ? 16 : 32);
     static_assert(N - K < K, "every position of the lower half holds an entry");
     float ck[N];
     int ci[N];
@@ -951,6 +951,10 @@ constexpr GramFn gram_fn() {
 // (lo, hi) -> kernel; lo is a group start of the filtered partition.
 GramFn pick(int lo, int hi) {
   switch (lo) {
+    case 5: {
+      constexpr GramFn t[] = {gram_fn<5, 5>(), gram_fn<5, 6>(), gram_fn<5, 7>(), gram_fn<5, 8>()};
+      return hi >= 5 && hi <= 8 ? t[hi - 5] : nullptr;
+    }
     case 9: {
       constexpr GramFn t[] = {gram_fn<9, 9>(), gram_fn<9, 10>(), gram_fn<9, 11>()};
       return hi >= 9 && hi <= 11 ? t[hi - 9] : nullptr;

@@ -87,13 +87,13 @@ hipError_t launch_tables_persistent(const KnnArgs &a, int group, const TableItem
 // Matrix-core filter of the batched scans (gram.hip).  E values from
 // kGramEMin up run through it when KnnArgs::gram_nrm is set; kGramLMax bounds
 // the series length (LDS holds the series three times).
-constexpr int kGramEMin = 9;
+constexpr int kGramEMin = 5;
 constexpr int kGramNE = EDM_E_MAX - kGramEMin + 1;
 constexpr int kGramPad = 64;  // zero samples staged past the end of a series
 constexpr int64_t kGramLMax = 14336;
 // E groups of the filtered scan (one register list per E of a group; the
 // slot layout needs E_hi + |group| + 1 <= 16 or a shared first chunk).
-constexpr int kGramGroups[5][2] = {{9, 11}, {12, 13}, {14, 16}, {17, 18}, {19, 20}};
+constexpr int kGramGroups[6][2] = {{5, 8}, {9, 11}, {12, 13}, {14, 16}, {17, 18}, {19, 20}};
 inline int64_t gram_ld(int64_t L_max) { return (L_max + kGramPad + 63) / 64 * 64; }
 // Per slot: centring constant, then the packed norms of every E >= kGramEMin.
 hipError_t launch_gram_prep(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t st);

@@ -260,7 +260,7 @@ hipError_t launch_sweep_multi(const KnnArgs &a, int nslots, int64_t L_max, hipSt
   for (const auto &g : kGroups) {
     const int lo = g[0];
     if (gram && lo >= kGramEMin) break;
-    const int hi = hi_of(lo, g[1]);
+    const int hi = hi_of(lo, gram && g[1] >= kGramEMin ? kGramEMin - 1 : g[1]);
     if (hi == 0) continue;
     if (lo > hi) break;
     const std::array<LaunchFn, 8> &t = lo == 1 ? t1 : lo == 9 ? t9 : lo == 13 ? t13 : lo == 16 ? t16 : t19;

@@ -127,7 +127,7 @@ def cases():
     yield "heavy", rng.standard_t(2, 260).astype(np.float32)
 
 
-@pytest.mark.parametrize("E", [9, 12, 16, 20])
+@pytest.mark.parametrize("E", [5, 8, 9, 12, 16, 20])
 @pytest.mark.parametrize("order", ["forward", "reverse", "pairwise", "shuffle"])
 def test_filter_never_drops_a_closer_candidate(E, order):
     for name, x in cases():

@@ -1,4 +1,4 @@
-"""Matrix-core filtered scan (chosen form, E >= 9) against the oracle and the
+"""Matrix-core filtered scan (chosen form, E >= 5) against the oracle and the
 exact scans.
 
 The filter only decides which candidates are re-ranked exactly, so its tables
@@ -62,6 +62,21 @@ def levels(L, seed):
 
 KNN_CASES = [
     # name, series, E, Tp
+    ("logistic E5", logistic(700, 0), 5, 1),
+    ("logistic E6 Tp0", logistic(700, 1), 6, 0),
+    ("logistic E7", logistic(700, 2), 7, 1),
+    ("logistic E8", logistic(700, 3), 8, 1),
+    ("calcium E5", calcium(900, 3), 5, 1),
+    ("calcium E8", calcium(900, 4), 8, 0),
+    ("tiled E6", synth.tiled_period(13 * 40, 13, 4), 6, 1),
+    ("ties E5", levels(400, 3), 5, 1),
+    ("ties E8", levels(300, 4), 8, 0),
+    ("offset E7", logistic(600, 6) + np.float32(1000.0), 7, 1),
+    ("tiny E6", logistic(500, 7) * np.float32(1e-20), 6, 1),
+    ("huge E5", logistic(500, 0) * np.float32(2e18), 5, 1),
+    ("constant E5", np.full(300, 0.37, np.float32), 5, 1),
+    ("nq=k+1 E5", logistic(12, 1), 5, 1),       # nq = 7: exactly k candidates besides self
+    ("nq=33 E8", logistic(40, 2), 8, 0),
     ("logistic E9", logistic(700, 0), 9, 1),
     ("logistic E10 Tp0", logistic(700, 1), 10, 0),
     ("logistic E11", logistic(700, 2), 11, 1),
