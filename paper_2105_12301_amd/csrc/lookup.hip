@@ -14,9 +14,9 @@
 // and every form are bit-identical.
 //
 // Grid kernel: a workgroup stages a tile of T targets of one E (the window
-// [t(0)+Tp, t(nq-1)+Tp] the tables can touch) and its 4 waves run 4
+// [t(0)+Tp, t(nq-1)+Tp] the tables can touch) and its 8 waves run 8
 // libraries' tables against them, each wave reusing every table row for the
-// T targets.  Work-list kernel: one item (library, T <= 16 targets) per
+// T targets (8 waves: two workgroups of 64 KB staging fill a CU with 16 waves).  Work-list kernel: one item (library, T <= 16 targets) per
 // workgroup; wave w takes targets 4w .. 4w+3 in one table pass.
 #include <array>
 #include <utility>
@@ -32,6 +32,8 @@ constexpr int kTMax = 8;               // targets per grid workgroup, upper boun
 constexpr int kItemTMax = kLookupItemMaxTargets;
 constexpr int kWaveT = kItemTMax / (kLookupThreads / 64);  // targets per wave in an item
 constexpr int kLookupWaves = kLookupThreads / kWave;
+constexpr int kGridWaves = 8;  // libraries per grid workgroup (one wave each)
+constexpr int kGridThreads = kGridWaves * kWave;
 constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS for staged targets
 
 struct Sums {
@@ -125,21 +127,21 @@ __device__ __forceinline__ void stage_targets(const LookupArgs &a, const int *tg
   if (bad) atomicOr(a.status, 1);
 }
 
-// Grid kernel: blockIdx.x = tile of T targets, blockIdx.y = group of 4
-// library slots; ms = LDS row stride (>= every staged window).
+// Grid kernel: blockIdx.x = tile of T targets, blockIdx.y = group of
+// kGridWaves library slots; ms = LDS row stride (>= every staged window).
 template <int K>
-__global__ __launch_bounds__(kLookupThreads) void k_lookup(LookupArgs a, int T, int ms,
+__global__ __launch_bounds__(kGridThreads) void k_lookup(LookupArgs a, int T, int ms,
                                                            int nslots, int slot0) {
   extern __shared__ float ys[];  // [T][ms]
   const int t0 = static_cast<int>(blockIdx.x) * T;
-  const int sbase = slot0 + static_cast<int>(blockIdx.y) * kLookupWaves;
+  const int sbase = slot0 + static_cast<int>(blockIdx.y) * kGridWaves;
   const int off = (a.E - 1) * a.tau + a.Tp;
   int tgt[kTMax];
   const int Tn = a.ntgt - t0 < T ? a.ntgt - t0 : T;
 #pragma unroll
   for (int t = 0; t < kTMax; ++t) tgt[t] = t < Tn ? (a.tgt_ids ? a.tgt_ids[t0 + t] : t0 + t) : 0;
   int n_blk = 0;  // widest query range of the workgroup's libraries
-  for (int w = 0; w < kLookupWaves; ++w) {
+  for (int w = 0; w < kGridWaves; ++w) {
     const int slot = sbase + w;
     if (slot >= slot0 + nslots) break;
     const int lib = a.lib_ids ? a.lib_ids[slot] : slot;
@@ -252,7 +254,7 @@ hipError_t launch_k(const LookupArgs &a, dim3 grid, size_t shm, int T, int ms, i
                                        static_cast<int>(shm));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_lookup<K>), grid, dim3(kLookupThreads), shm, st, a, T, ms, nslots, slot0);
+  hipLaunchKernelGGL((k_lookup<K>), grid, dim3(kGridThreads), shm, st, a, T, ms, nslots, slot0);
   return hipGetLastError();
 }
 
@@ -273,10 +275,10 @@ hipError_t launch_lookup(const LookupArgs &a, int nslots, int64_t m_max, hipStre
   const int ms = static_cast<int>(m_max);
   const size_t shm = static_cast<size_t>(T) * static_cast<size_t>(m_max) * sizeof(float);
   const unsigned gx = static_cast<unsigned>((a.ntgt + T - 1) / T);
-  constexpr int kMaxY = 32768 * kLookupWaves;
+  constexpr int kMaxY = 32768 * kGridWaves;
   for (int s0 = 0; s0 < nslots; s0 += kMaxY) {
     const int ns = nslots - s0 < kMaxY ? nslots - s0 : kMaxY;
-    const unsigned gy = static_cast<unsigned>((ns + kLookupWaves - 1) / kLookupWaves);
+    const unsigned gy = static_cast<unsigned>((ns + kGridWaves - 1) / kGridWaves);
     hipError_t e = table[a.k - 1](a, dim3(gx, gy), shm, T, ms, ns, s0, st);
     if (e != hipSuccess) return e;
   }
