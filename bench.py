@@ -37,7 +37,7 @@ ALU_PEAK_OPS = 256 * 128 * 2.4e9
 # HBM bytes of one chosen-form sweep on this workload from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0), the scales a 256 MiB device copy
 # gives the two counters (profiles/chosen_sweep_ccm_logistic1024_L5000.md).
-SWEEP_TRAFFIC_BYTES = 3.30e9
+SWEEP_TRAFFIC_BYTES = 4.20e9
 
 WORKLOAD = dict(name="logistic-network", N=1024, L=5000, E_max=20, tau=1, Tp_sweep=1,
                 Tp_ccm=0, seed=2)
