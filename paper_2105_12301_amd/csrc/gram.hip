@@ -941,6 +941,33 @@ __global__ __launch_bounds__(256) void k_gram_norms(KnnArgs a) {
   }
 }
 
+// Work-list form: workgroups pull (row, block) items until the list is
+// exhausted (every workgroup reaches the exit); one workgroup per item when
+// counter is null.
+template <int ELO, int EHI>
+__global__ __launch_bounds__(kGramThreads) void k_gram_persistent(KnnArgs a,
+                                                                  const TableItem *__restrict__ items,
+                                                                  int n_items, int *counter) {
+  extern __shared__ float gram_smem[];
+  __shared__ int item_s;
+  for (int trip = 0;; ++trip) {
+    int it;
+    if (counter == nullptr) {
+      if (trip > 0) break;
+      it = static_cast<int>(blockIdx.x);
+    } else {
+      __syncthreads();  // the previous item is done with the LDS arrays and item_s
+      if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
+      __syncthreads();
+      it = __builtin_amdgcn_readfirstlane(item_s);
+      if (it >= n_items) break;
+    }
+    const int row = __builtin_amdgcn_readfirstlane(items[it].row);
+    const int blk = __builtin_amdgcn_readfirstlane(static_cast<int>(items[it].blk));
+    gram_scan<ELO, EHI>(a, row, blk, gram_smem);
+  }
+}
+
 using GramFn = void (*)(KnnArgs, int);
 
 template <int LO, int HI>
@@ -990,6 +1017,38 @@ hipError_t launch_gram_prep(const KnnArgs &a, int nslots, int64_t L_max, hipStre
   if (e != hipSuccess) return e;
   const unsigned gx = static_cast<unsigned>((a.gram_ld + 255) / 256);
   hipLaunchKernelGGL(k_gram_norms, dim3(gx, static_cast<unsigned>(nslots)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_persistent(const KnnArgs &a, int g, const TableItem *items, int n_items,
+                                  int *counter, int64_t L_max, int wg_per_cu, int n_cu,
+                                  hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  using Fn = void (*)(KnnArgs, const TableItem *, int, int *);
+  static const Fn fns[6] = {&k_gram_persistent<5, 8>,   &k_gram_persistent<9, 11>,
+                            &k_gram_persistent<12, 13>, &k_gram_persistent<14, 16>,
+                            &k_gram_persistent<17, 18>, &k_gram_persistent<19, 20>};
+  static_assert(sizeof(kGramGroups) / sizeof(kGramGroups[0]) == 6, "one kernel per filtered group");
+  if (g < 0 || g > 5 || L_max > kGramLMax || a.gram_ld < L_max + kGramPad || a.tau != 1 ||
+      a.mom != nullptr)
+    return hipErrorInvalidValue;
+  const size_t shm = static_cast<size_t>(a.gram_ld) * (sizeof(float) + 2 * sizeof(uint16_t)) +
+                     sizeof(uint32_t) * kQueueCap * kGramThreads;
+  const void *fn = reinterpret_cast<const void *>(fns[g]);
+  if (shm > 65536) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(shm));
+    if (e != hipSuccess) return e;
+  }
+  if (wg_per_cu <= 0) {
+    hipLaunchKernelGGL(fns[g], dim3(static_cast<unsigned>(n_items)), dim3(kGramThreads), shm, st, a,
+                       items, n_items, static_cast<int *>(nullptr));
+    return hipGetLastError();
+  }
+  int grid = wg_per_cu * n_cu;
+  if (grid > n_items) grid = n_items;
+  hipLaunchKernelGGL(fns[g], dim3(static_cast<unsigned>(grid)), dim3(kGramThreads), shm, st, a,
+                     items, n_items, counter);
   return hipGetLastError();
 }
 

@@ -80,6 +80,7 @@ struct LookupItem {
 // Persistent table kernel of one E group (0: E 1-8, 1: 9-12, 2: 13-15,
 // 3: 16-18, 4: 19-20) over its work list (counter: a device int that starts
 // at 0).
+// group: 0-4 the exact E groups {1-8, 9-12, 13-15, 16-18, 19-20}; 5: E 1-4.
 hipError_t launch_tables_persistent(const KnnArgs &a, int group, const TableItem *items,
                                     int n_items, int *counter, int64_t L_max, int wg_per_cu,
                                     int n_cu, hipStream_t st);
@@ -101,6 +102,12 @@ hipError_t launch_gram_prep(const KnnArgs &a, int nslots, int64_t L_max, hipStre
 // same outputs as launch_sweep_multi.
 hipError_t launch_gram_group(const KnnArgs &a, int lo, int hi, int nslots, int64_t L_max,
                              hipStream_t st);
+// Work-list form for the plan: items (row, blk) of filtered group g
+// (kGramGroups[g]), table mode; same outputs as launch_tables_persistent.
+// L_max bounds the rows of the items; a.gram_ld must be >= L_max + kGramPad.
+hipError_t launch_gram_persistent(const KnnArgs &a, int g, const TableItem *items, int n_items,
+                                  int *counter, int64_t L_max, int wg_per_cu, int n_cu,
+                                  hipStream_t st);
 
 // Cross-map tables (Tp = 0) of dimension E for `nslots` libraries from the
 // sweep's lists (Tp = 1) in a.keepE[E]; output in a.idxE[E] / a.wE[E] with

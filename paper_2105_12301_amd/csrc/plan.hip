@@ -27,15 +27,38 @@ using namespace edm::host;
 
 namespace {
 
+// Table work lists: the exact E groups (lists 0-4), the exact E 1-4 below
+// the filter (list 5), and the matrix-core filtered groups of the chosen form
+// (lists 6-11, kGramGroups).  A library up to kGramLMax samples in the chosen
+// form takes lists 5-11, any other library lists 0-4.
 constexpr int kNGroups = 5;
 constexpr int kGroupLo[kNGroups] = {1, 9, 13, 16, 19};
 constexpr int kGroupHi[kNGroups] = {8, 12, 15, 18, 20};
+constexpr int kNGram = 6;
+constexpr int kNLists = kNGroups + 1 + kNGram;
 
 struct Batch {
-  int64_t L_max = 0;
-  std::array<int64_t, kNGroups> t_begin{}, t_count{};
+  int64_t L_max = 0, Lg_max = 0;  // longest library; longest filtered library
+  std::array<int64_t, kNLists> t_begin{}, t_count{};
   std::array<int64_t, EDM_E_MAX + 1> l_begin{}, l_count{}, lds_floats{};
 };
+
+// E range and eligibility of table list c for a library (filtered or not).
+inline bool list_range(int c, bool filt, int &lo, int &hi) {
+  if (c < kNGroups) {
+    lo = kGroupLo[c];
+    hi = kGroupHi[c];
+    return !filt;
+  }
+  if (c == kNGroups) {
+    lo = 1;
+    hi = edm::kGramEMin - 1;
+    return filt;
+  }
+  lo = edm::kGramGroups[c - kNGroups - 1][0];
+  hi = edm::kGramGroups[c - kNGroups - 1][1];
+  return filt;
+}
 
 }  // namespace
 
@@ -54,6 +77,10 @@ struct edm_plan {
   float *tbl_w = nullptr;
   edm::TableItem *titems = nullptr;
   edm::LookupItem *litems = nullptr;
+  bool filtered = false;  // some library runs through the matrix-core filter
+  int64_t Lg_max = 0, gram_ld = 0;
+  float *gram_mu = nullptr;
+  uint32_t *gram_nrm = nullptr;
   std::vector<Batch> batches;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -133,6 +160,10 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
     return std::partition_point(b.begin(), b.end(), [&](int32_t j) { return Ly[j] >= L; }) - b.begin();
   };
 
+  // Chosen form: libraries up to kGramLMax samples use the filter for E >= kGramEMin.
+  const bool chosen = ctx->form == EDM_FORM_CHOSEN;
+  auto filt_of = [&](int64_t i) { return chosen && Lx[i] <= edm::kGramLMax; };
+
   // Libraries longest first; per library the E it needs and their table sizes.
   std::vector<int32_t> order(static_cast<size_t>(Nl));
   std::iota(order.begin(), order.end(), 0);
@@ -176,6 +207,7 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
     for (int64_t q = k0; q < k; ++q) {
       const int32_t i = order[static_cast<size_t>(q)];
       B.L_max = std::max(B.L_max, Lx[i]);
+      if (filt_of(i)) B.Lg_max = std::max(B.Lg_max, Lx[i]);
       for (int E = 1; E <= EDM_E_MAX; ++E) {
         if (!((need[static_cast<size_t>(i)] >> (E - 1)) & 1u)) continue;
         tbl_off[static_cast<size_t>(i) * (EDM_E_MAX + 1) + E] = o;
@@ -183,20 +215,23 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
         o += static_cast<int64_t>(align_up(static_cast<size_t>(m) * (E + 1) * 4, 256)) / 4;
       }
     }
-    // table items, per group, longest library first
-    for (int g = 0; g < kNGroups; ++g) {
-      B.t_begin[g] = static_cast<int64_t>(titems.size());
+    // table items, per list, longest library first (a filtered block also
+    // covers kKnnThreads queries)
+    for (int c = 0; c < kNLists; ++c) {
+      B.t_begin[c] = static_cast<int64_t>(titems.size());
       for (int64_t q = k0; q < k; ++q) {
         const int32_t i = order[static_cast<size_t>(q)];
+        int lo = 0, hi = 0;
+        if (!list_range(c, filt_of(i), lo, hi)) continue;
         uint32_t gm = 0;
-        for (int E = kGroupLo[g]; E <= kGroupHi[g]; ++E) gm |= need[static_cast<size_t>(i)] & (1u << (E - 1));
+        for (int E = lo; E <= hi; ++E) gm |= need[static_cast<size_t>(i)] & (1u << (E - 1));
         if (!gm) continue;
-        const int64_t m_lo = Lx[i] - (kGroupLo[g] - 1) - Tp;
+        const int64_t m_lo = Lx[i] - (lo - 1) - Tp;
         const int64_t nb = (m_lo + edm::kKnnThreads - 1) / edm::kKnnThreads;
         for (int64_t b = 0; b < nb; ++b)
-          titems.push_back(edm::TableItem{i, static_cast<int16_t>(g), static_cast<int16_t>(b)});
+          titems.push_back(edm::TableItem{i, static_cast<int16_t>(c), static_cast<int16_t>(b)});
       }
-      B.t_count[g] = static_cast<int64_t>(titems.size()) - B.t_begin[g];
+      B.t_count[c] = static_cast<int64_t>(titems.size()) - B.t_begin[c];
     }
     // lookup items, per E, longest library first
     for (int E = 1; E <= EDM_E_MAX; ++E) {
@@ -217,7 +252,10 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
     }
     P->batches.push_back(B);
   }
-  P->n_counters = static_cast<int>(P->batches.size()) * (kNGroups + EDM_E_MAX);
+  P->n_counters = static_cast<int>(P->batches.size()) * (kNLists + EDM_E_MAX);
+  for (const Batch &B : P->batches) P->Lg_max = std::max(P->Lg_max, B.Lg_max);
+  P->filtered = P->Lg_max > 0;
+  P->gram_ld = P->filtered ? edm::gram_ld(P->Lg_max) : 0;
 
   // One device allocation: lengths, masks, offsets, buckets, counters,
   // items, and the table buffer of the largest batch.
@@ -234,6 +272,10 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
   const size_t small = lay.bytes;
   const size_t oTidx = lay.take(sizeof(int32_t) * max_batch_elems);
   const size_t oTw = lay.take(sizeof(float) * max_batch_elems);
+  // filter prep of every library: centring constants and packed norms
+  const size_t oGmu = P->filtered ? lay.take(sizeof(float) * Nl) : 0;
+  const size_t oGnrm =
+      P->filtered ? lay.take(sizeof(uint32_t) * static_cast<size_t>(Nl) * edm::kGramNE * P->gram_ld) : 0;
   if (hipMalloc(reinterpret_cast<void **>(&P->dev), lay.bytes) != hipSuccess) {
     (void)hipGetLastError();
     P->dev = nullptr;
@@ -251,6 +293,10 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
   P->litems = reinterpret_cast<edm::LookupItem *>(P->dev + oLi);
   P->tbl_idx = reinterpret_cast<int32_t *>(P->dev + oTidx);
   P->tbl_w = reinterpret_cast<float *>(P->dev + oTw);
+  if (P->filtered) {
+    P->gram_mu = reinterpret_cast<float *>(P->dev + oGmu);
+    P->gram_nrm = reinterpret_cast<uint32_t *>(P->dev + oGnrm);
+  }
   std::vector<char> blob(small, 0);
   std::memcpy(blob.data() + oLx, Lx, sizeof(int64_t) * Nl);
   std::memcpy(blob.data() + oLy, Ly, sizeof(int64_t) * Nt);
@@ -280,24 +326,36 @@ int enqueue_plan(edm_ctx *ctx, edm_plan *P, const float *X, const float *Y, floa
   EDM_HIP(ctx, edm::launch_fill(rho, P->Nl * P->Nt, __builtin_nanf(""), st));
   // counters start at 0: an all-zero float fill writes zero bits
   EDM_HIP(ctx, edm::launch_fill(reinterpret_cast<float *>(P->counters), P->n_counters, 0.0f, st));
+  edm::KnnArgs a{};
+  a.X = X;
+  a.ldx = P->ldx;
+  a.L_dev = P->Lx_dev;
+  a.tau = 1;
+  a.Tp = P->Tp;
+  a.E_max = EDM_E_MAX;
+  a.status = ctx->status;
+  a.need_dev = P->need;
+  a.tbl_off = P->tbl_off;
+  a.tbl_idx = P->tbl_idx;
+  a.tbl_w = P->tbl_w;
+  if (P->filtered) {
+    a.gram_mu = P->gram_mu;
+    a.gram_nrm = P->gram_nrm;
+    a.gram_ld = P->gram_ld;
+    EDM_HIP(ctx, edm::launch_gram_prep(a, static_cast<int>(P->Nl), P->Lg_max, st));
+  }
   int c = 0;
   for (const Batch &B : P->batches) {
-    edm::KnnArgs a{};
-    a.X = X;
-    a.ldx = P->ldx;
-    a.L_dev = P->Lx_dev;
-    a.tau = 1;
-    a.Tp = P->Tp;
-    a.E_max = EDM_E_MAX;
-    a.status = ctx->status;
-    a.need_dev = P->need;
-    a.tbl_off = P->tbl_off;
-    a.tbl_idx = P->tbl_idx;
-    a.tbl_w = P->tbl_w;
-    for (int g = 0; g < kNGroups; ++g, ++c)
+    for (int g = 0; g <= kNGroups; ++g, ++c)
       EDM_HIP(ctx, edm::launch_tables_persistent(a, g, P->titems + B.t_begin[g], static_cast<int>(B.t_count[g]),
                                                  P->counters + c, B.L_max, P->tune.tables_wg_per_cu,
                                                  P->n_cu, st));
+    for (int f = 0; f < kNGram; ++f, ++c) {
+      const int l = kNGroups + 1 + f;
+      EDM_HIP(ctx, edm::launch_gram_persistent(a, f, P->titems + B.t_begin[l], static_cast<int>(B.t_count[l]),
+                                               P->counters + c, B.Lg_max, P->tune.tables_wg_per_cu,
+                                               P->n_cu, st));
+    }
     edm::LookupArgs b{};
     b.Lx_dev = P->Lx_dev;
     b.tau = 1;

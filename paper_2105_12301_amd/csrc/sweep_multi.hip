@@ -289,10 +289,11 @@ hipError_t launch_tables_persistent(const KnnArgs &a, int group, const TableItem
                                     int n_cu, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   using Fn = void (*)(KnnArgs, const TableItem *, int, int *);
-  static const Fn fns[5] = {&k_tables_persistent<1, 8>, &k_tables_persistent<9, 12>,
+  // groups 0-4: the exact E groups; 5: E 1-4 (below the filtered groups)
+  static const Fn fns[6] = {&k_tables_persistent<1, 8>, &k_tables_persistent<9, 12>,
                             &k_tables_persistent<13, 15>, &k_tables_persistent<16, 18>,
-                            &k_tables_persistent<19, 20>};
-  if (group < 0 || group > 4) return hipErrorInvalidValue;
+                            &k_tables_persistent<19, 20>, &k_tables_persistent<1, 4>};
+  if (group < 0 || group > 5) return hipErrorInvalidValue;
   const size_t shm = static_cast<size_t>(L_max) * sizeof(float);
   const void *fn = reinterpret_cast<const void *>(fns[group]);
   if (shm > 65536) {

@@ -57,6 +57,35 @@ def test_plan_equals_ccm_bitwise(edm, side, tune, limit, monkeypatch):
         ctx.close()
 
 
+@pytest.mark.parametrize("tune", TUNES[:2], ids=["grid", "persistent-1"])
+def test_chosen_plan_equals_plain_ccm_bitwise(edm, side, tune):
+    # In the chosen form the plan's tables for E >= 5 come from the matrix-core
+    # filter for libraries up to 14336 samples and from the exact scan for
+    # longer ones; every rho must equal the plain form's bit for bit.
+    from paper_2105_12301_amd.autotune import make_tune
+    X, lens, E = synth.spike_trains(seed=22, N=40, L_min=150, L_max=1400)
+    Xw = np.zeros((X.shape[0] + 2, 14400), np.float32)
+    Xw[:X.shape[0], :X.shape[1]] = X
+    long_x, _, _ = synth.logistic_network(seed=23, N=4, L=14400)
+    Xw[-2:] = long_x[:2]
+    lens = np.concatenate([lens, [14336, 14400]]).astype(np.int64)
+    E = np.concatenate([E, [7, 12]]).astype(np.int32)
+    E[3] = 0
+    with torch.cuda.stream(side):
+        ctx = edm.Context(device=0, stream=side, form=edm.EDM_FORM_PLAIN)
+        Xd = dev(Xw)
+        ref = edm.edm_ccm(Xd, dev(E), Lx=lens, Ly=lens, ctx=ctx)
+        ctx.set_form(edm.EDM_FORM_CHOSEN)
+        plan = edm.CcmPlan(lens, lens, E, Xw.shape[1], Xw.shape[1], tune=make_tune(tune), ctx=ctx)
+        r1 = plan.run(Xd).clone()
+        r2 = plan.run(Xd).clone()
+        ctx.sync()
+        assert torch.equal(ref.view(torch.int32), r1.view(torch.int32))
+        assert torch.equal(r1.view(torch.int32), r2.view(torch.int32))
+        plan.close()
+        ctx.close()
+
+
 def test_plan_matches_oracle_and_default_stream(edm):
     X, lens, E = synth.spike_trains(seed=22, N=20, L_min=200, L_max=900)
     ctx = edm.Context(device=0)   # legacy stream: enqueued without a graph
