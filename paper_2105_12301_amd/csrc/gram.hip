@@ -312,7 +312,8 @@ __device__ __forceinline__ bool lex_less(float ka, int ia, float kb, int ib) {
 // and E1 = E0 + 1 (or E0 alone when E1 == E0): the same float64 arithmetic,
 // in the same order, as finish_list, with the lag and neighbour counts set
 // at run time so that the two lane halves finish two dimensions at once.
-// idx: the sorted list (E + 1 entries used); the query's samples come from xs.
+// idx: the sorted list (E + 1 entries used); the query's samples come from xs
+// (LDS or global: every index read here lies inside the series).
 template <int E0, int E1>
 __device__ __forceinline__ Mom finish_round(const KnnArgs &a, int row, int p, int L, int Tp,
                                             uint32_t need, const int (&idx)[E1 + 1], int E,
@@ -396,7 +397,9 @@ __device__ __forceinline__ Mom finish_round(const KnnArgs &a, int row, int p, in
 
 // One workgroup's share of a filtered scan: query block `bx` of row `row`,
 // every E in [ELO, EHI].  Same outputs as the exact group scan.
-template <int ELO, int EHI>
+// XG: the exact float32 samples are read from global memory (L2) instead of
+// an LDS copy, which leaves room in LDS for series up to kGramLMax.
+template <int ELO, int EHI, bool XG>
 __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const int bx,
                                           float *__restrict__ smem) {
   using Lay = Layout<ELO, EHI>;
@@ -415,9 +418,15 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   if (blk0 >= m_lo) return;
 
   const int64_t ld = a.gram_ld;
-  float *xs = smem;
-  uint16_t *xh = reinterpret_cast<uint16_t *>(smem + ld);
+  float *xs = smem;  // unused when XG
+  uint16_t *xh = reinterpret_cast<uint16_t *>(XG ? smem : smem + ld);
   uint16_t *xl = xh + ld;
+  // exact samples: LDS copy (zero past L), or the global row with the index
+  // clamped to the row (clamped reads only feed keys that are discarded)
+  auto xat = [&](int i) -> float {
+    if constexpr (XG) return x[i < L ? i : L - 1];
+    else return xs[i];
+  };
   const uint32_t *xh32 = reinterpret_cast<const uint32_t *>(xh);
   const uint32_t *xl32 = reinterpret_cast<const uint32_t *>(xl);
   uint32_t *qbuf_all = reinterpret_cast<uint32_t *>(xl + ld);  // [wave][kQueueCap][64] queues
@@ -434,7 +443,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
       b = v - mu;
     }
     big |= !(fabsf(b) <= kGramSafeMax);
-    xs[i] = v;
+    if constexpr (!XG) xs[i] = v;
     const uint32_t pk = split_pack(b);
     xh[i] = static_cast<uint16_t>(pk & 0xffffu);
     xl[i] = static_cast<uint16_t>(pk >> 16);
@@ -552,7 +561,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     float acc = 0.0f;
     static_for<0, EHI - 1>([&](auto JC) {
       constexpr int j = decltype(JC)::value;
-      const float d = xs[pc + j] - xs[q + j];
+      const float d = xat(pc + j) - xat(q + j);
       acc = acc + d * d;
       if constexpr (j + 1 >= ELO) {
         constexpr int E = j + 1;
@@ -565,9 +574,9 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     float a0 = 0.0f, a1 = 0.0f;
     static_for<0, EHI - 1>([&](auto JC) {
       constexpr int j = decltype(JC)::value;
-      const float xp = xs[pc + j];
-      const float d0 = xp - xs[q0 + j];
-      const float d1 = xp - xs[q1 + j];
+      const float xp = xat(pc + j);
+      const float d0 = xp - xat(q0 + j);
+      const float d1 = xp - xat(q1 + j);
       a0 = a0 + d0 * d0;
       a1 = a1 + d1 * d1;
       if constexpr (j + 1 >= ELO) {
@@ -588,10 +597,10 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
 #pragma unroll
   for (int g = 0; g < NG; ++g) ub[g] = __builtin_inff();
   if (pw < m_lo) {
-    // The tile index replaces the 9 low mantissa bits of the estimate (a
-    // relative change below 2^-14: the ranking only picks candidates), so one
+    // The tile index replaces the 10 low mantissa bits of the estimate (a
+    // relative change below 2^-13: the ranking only picks candidates), so one
     // minimum keeps the estimate and its tile.  The estimates are finite.
-    static_assert(kGramLMax / 32 <= 0x1ff, "tile index field");
+    static_assert(kGramLMax / 32 <= 0x3ff, "tile index field");
     float bm[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) bm[v] = __builtin_inff();
@@ -638,8 +647,8 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
       const uint32_t tA = static_cast<uint32_t>(c0) >> 5, tB = static_cast<uint32_t>(cb) >> 5;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const float eA = __uint_as_float((__float_as_uint(accA[v]) & ~0x1ffu) | tA);
-        const float eB = __uint_as_float((__float_as_uint(accB[v]) & ~0x1ffu) | tB);
+        const float eA = __uint_as_float((__float_as_uint(accA[v]) & ~0x3ffu) | tA);
+        const float eB = __uint_as_float((__float_as_uint(accB[v]) & ~0x3ffu) | tB);
         bm[v] = vmin(bm[v], vmin(eA, eB));
       }
     }
@@ -647,7 +656,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const bool won = bm[v] != __builtin_inff();
-      const int bt = won ? static_cast<int>(__float_as_uint(bm[v]) & 0x1ffu) * 32 : -1;
+      const int bt = won ? static_cast<int>(__float_as_uint(bm[v]) & 0x3ffu) * 32 : -1;
       const int q = bt + 8 * (v >> 2) + (h1 ? 4 : 0) + (v & 3);
       float key[NG];
       exact_keys(bt < 0 ? 0 : q, bt >= 0 && q != p, key);
@@ -710,7 +719,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   // Two survivors per step (where the register budget allows): their key
   // chains are independent and overlap; they are inserted in order, so each
   // list still sees ascending q.
-  constexpr int kStep = TOT <= 44 ? 2 : 1;
+  constexpr int kStep = (TOT <= 44 && !XG) ? 2 : 1;
   auto flush = [&]() {
     const int n_iter = (wave_max(nsv) + kStep - 1) / kStep;
     int j = 0;
@@ -874,7 +883,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
       idx[i] = up ? qi[list_off<ELO>(E1) + i] : lo_i;
     }
     Mom mine = mom_zero();
-    if (!h1 || up) mine = finish_round<E0, E1>(a, row, p, L, Tp, need, idx, up ? E1 : E0, xs);
+    if (!h1 || up) mine = finish_round<E0, E1>(a, row, p, L, Tp, need, idx, up ? E1 : E0, XG ? x : xs);
     if (a.mom) {  // uniform
 #pragma unroll
       for (int m = 1; m < 32; m <<= 1) mine = mom_merge(mine, mom_shfl_xor(mine, m));
@@ -897,11 +906,11 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   }
 }
 
-template <int ELO, int EHI>
+template <int ELO, int EHI, bool XG>
 __global__ __launch_bounds__(kGramThreads) void k_gram(KnnArgs a, int slot0) {
   extern __shared__ float gram_smem[];
-  gram_scan<ELO, EHI>(a, slot0 + static_cast<int>(blockIdx.y), static_cast<int>(blockIdx.x),
-                      gram_smem);
+  gram_scan<ELO, EHI, XG>(a, slot0 + static_cast<int>(blockIdx.y), static_cast<int>(blockIdx.x),
+                          gram_smem);
 }
 
 // Centring constant of each slot: the float32 mean (float64 sum).
@@ -941,70 +950,65 @@ __global__ __launch_bounds__(256) void k_gram_norms(KnnArgs a) {
   }
 }
 
-// Work-list form: workgroups pull (row, block) items until the list is
-// exhausted (every workgroup reaches the exit); one workgroup per item when
-// counter is null.
-template <int ELO, int EHI>
-__global__ __launch_bounds__(kGramThreads) void k_gram_persistent(KnnArgs a,
-                                                                  const TableItem *__restrict__ items,
-                                                                  int n_items, int *counter) {
+// Work-list form: one workgroup per (row, block) item.  (The filtered scan
+// fills a CU with one workgroup, so pulling items gains nothing, and a loop
+// around the scan costs registers.)
+template <int ELO, int EHI, bool XG>
+__global__ __launch_bounds__(kGramThreads) void k_gram_items(KnnArgs a,
+                                                             const TableItem *__restrict__ items) {
   extern __shared__ float gram_smem[];
-  __shared__ int item_s;
-  for (int trip = 0;; ++trip) {
-    int it;
-    if (counter == nullptr) {
-      if (trip > 0) break;
-      it = static_cast<int>(blockIdx.x);
-    } else {
-      __syncthreads();  // the previous item is done with the LDS arrays and item_s
-      if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
-      __syncthreads();
-      it = __builtin_amdgcn_readfirstlane(item_s);
-      if (it >= n_items) break;
-    }
-    const int row = __builtin_amdgcn_readfirstlane(items[it].row);
-    const int blk = __builtin_amdgcn_readfirstlane(static_cast<int>(items[it].blk));
-    gram_scan<ELO, EHI>(a, row, blk, gram_smem);
-  }
+  const int it = static_cast<int>(blockIdx.x);
+  const int row = __builtin_amdgcn_readfirstlane(items[it].row);
+  const int blk = __builtin_amdgcn_readfirstlane(static_cast<int>(items[it].blk));
+  gram_scan<ELO, EHI, XG>(a, row, blk, gram_smem);
 }
 
 using GramFn = void (*)(KnnArgs, int);
 
-template <int LO, int HI>
+template <int LO, int HI, bool XG>
 constexpr GramFn gram_fn() {
-  return &k_gram<LO, HI>;
+  return &k_gram<LO, HI, XG>;
 }
 
 // (lo, hi) -> kernel; lo is a group start of the filtered partition.
-GramFn pick(int lo, int hi) {
+template <bool XG>
+GramFn pick_xg(int lo, int hi) {
   switch (lo) {
     case 5: {
-      constexpr GramFn t[] = {gram_fn<5, 5>(), gram_fn<5, 6>(), gram_fn<5, 7>(), gram_fn<5, 8>()};
+      constexpr GramFn t[] = {gram_fn<5, 5, XG>(), gram_fn<5, 6, XG>(), gram_fn<5, 7, XG>(), gram_fn<5, 8, XG>()};
       return hi >= 5 && hi <= 8 ? t[hi - 5] : nullptr;
     }
     case 9: {
-      constexpr GramFn t[] = {gram_fn<9, 9>(), gram_fn<9, 10>(), gram_fn<9, 11>()};
+      constexpr GramFn t[] = {gram_fn<9, 9, XG>(), gram_fn<9, 10, XG>(), gram_fn<9, 11, XG>()};
       return hi >= 9 && hi <= 11 ? t[hi - 9] : nullptr;
     }
     case 12: {
-      constexpr GramFn t[] = {gram_fn<12, 12>(), gram_fn<12, 13>()};
+      constexpr GramFn t[] = {gram_fn<12, 12, XG>(), gram_fn<12, 13, XG>()};
       return hi >= 12 && hi <= 13 ? t[hi - 12] : nullptr;
     }
     case 14: {
-      constexpr GramFn t[] = {gram_fn<14, 14>(), gram_fn<14, 15>(), gram_fn<14, 16>()};
+      constexpr GramFn t[] = {gram_fn<14, 14, XG>(), gram_fn<14, 15, XG>(), gram_fn<14, 16, XG>()};
       return hi >= 14 && hi <= 16 ? t[hi - 14] : nullptr;
     }
     case 17: {
-      constexpr GramFn t[] = {gram_fn<17, 17>(), gram_fn<17, 18>()};
+      constexpr GramFn t[] = {gram_fn<17, 17, XG>(), gram_fn<17, 18, XG>()};
       return hi >= 17 && hi <= 18 ? t[hi - 17] : nullptr;
     }
     case 19: {
-      constexpr GramFn t[] = {gram_fn<19, 19>(), gram_fn<19, 20>()};
+      constexpr GramFn t[] = {gram_fn<19, 19, XG>(), gram_fn<19, 20, XG>()};
       return hi >= 19 && hi <= 20 ? t[hi - 19] : nullptr;
     }
     default:
       return nullptr;
   }
+}
+
+// Exact samples in LDS up to kGramLdsXsMax samples, read from global beyond.
+bool use_global_x(int64_t L_max) { return L_max > kGramLdsXsMax; }
+
+size_t gram_shm(int64_t ld, bool xg) {
+  return static_cast<size_t>(ld) * ((xg ? 0 : sizeof(float)) + 2 * sizeof(uint16_t)) +
+         sizeof(uint32_t) * kQueueCap * kGramThreads;
 }
 
 }  // namespace
@@ -1024,42 +1028,42 @@ hipError_t launch_gram_persistent(const KnnArgs &a, int g, const TableItem *item
                                   int *counter, int64_t L_max, int wg_per_cu, int n_cu,
                                   hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  using Fn = void (*)(KnnArgs, const TableItem *, int, int *);
-  static const Fn fns[6] = {&k_gram_persistent<5, 8>,   &k_gram_persistent<9, 11>,
-                            &k_gram_persistent<12, 13>, &k_gram_persistent<14, 16>,
-                            &k_gram_persistent<17, 18>, &k_gram_persistent<19, 20>};
+  (void)counter;
+  (void)wg_per_cu;
+  (void)n_cu;
+  using Fn = void (*)(KnnArgs, const TableItem *);
+  static const Fn fl[6] = {&k_gram_items<5, 8, false>,   &k_gram_items<9, 11, false>,
+                           &k_gram_items<12, 13, false>, &k_gram_items<14, 16, false>,
+                           &k_gram_items<17, 18, false>, &k_gram_items<19, 20, false>};
+  static const Fn fg[6] = {&k_gram_items<5, 8, true>,   &k_gram_items<9, 11, true>,
+                           &k_gram_items<12, 13, true>, &k_gram_items<14, 16, true>,
+                           &k_gram_items<17, 18, true>, &k_gram_items<19, 20, true>};
   static_assert(sizeof(kGramGroups) / sizeof(kGramGroups[0]) == 6, "one kernel per filtered group");
   if (g < 0 || g > 5 || L_max > kGramLMax || a.gram_ld < L_max + kGramPad || a.tau != 1 ||
       a.mom != nullptr)
     return hipErrorInvalidValue;
-  const size_t shm = static_cast<size_t>(a.gram_ld) * (sizeof(float) + 2 * sizeof(uint16_t)) +
-                     sizeof(uint32_t) * kQueueCap * kGramThreads;
+  const bool xg = use_global_x(a.gram_ld - kGramPad);
+  const Fn *fns = xg ? fg : fl;
+  const size_t shm = gram_shm(a.gram_ld, xg);
   const void *fn = reinterpret_cast<const void *>(fns[g]);
   if (shm > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(shm));
     if (e != hipSuccess) return e;
   }
-  if (wg_per_cu <= 0) {
-    hipLaunchKernelGGL(fns[g], dim3(static_cast<unsigned>(n_items)), dim3(kGramThreads), shm, st, a,
-                       items, n_items, static_cast<int *>(nullptr));
-    return hipGetLastError();
-  }
-  int grid = wg_per_cu * n_cu;
-  if (grid > n_items) grid = n_items;
-  hipLaunchKernelGGL(fns[g], dim3(static_cast<unsigned>(grid)), dim3(kGramThreads), shm, st, a,
-                     items, n_items, counter);
+  hipLaunchKernelGGL(fns[g], dim3(static_cast<unsigned>(n_items)), dim3(kGramThreads), shm, st, a,
+                     items);
   return hipGetLastError();
 }
 
 hipError_t launch_gram_group(const KnnArgs &a, int lo, int hi, int nslots, int64_t L_max,
                              hipStream_t st) {
   if (nslots <= 0) return hipSuccess;
-  const GramFn fn = pick(lo, hi);
+  const bool xg = use_global_x(a.gram_ld - kGramPad);
+  const GramFn fn = xg ? pick_xg<true>(lo, hi) : pick_xg<false>(lo, hi);
   if (fn == nullptr || L_max > kGramLMax || a.gram_ld < L_max + kGramPad || a.tau != 1)
     return hipErrorInvalidValue;
-  const size_t shm = static_cast<size_t>(a.gram_ld) * (sizeof(float) + 2 * sizeof(uint16_t)) +
-                     sizeof(uint32_t) * kQueueCap * kGramThreads;
+  const size_t shm = gram_shm(a.gram_ld, xg);
   const void *f = reinterpret_cast<const void *>(fn);
   if (shm > 65536) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -87,11 +87,13 @@ hipError_t launch_tables_persistent(const KnnArgs &a, int group, const TableItem
 
 // Matrix-core filter of the batched scans (gram.hip).  E values from
 // kGramEMin up run through it when KnnArgs::gram_nrm is set; kGramLMax bounds
-// the series length (LDS holds the series three times).
+// the series length (LDS holds the BF16 halves of the series, and its float32
+// samples up to kGramLdsXsMax).
 constexpr int kGramEMin = 5;
 constexpr int kGramNE = EDM_E_MAX - kGramEMin + 1;
 constexpr int kGramPad = 64;  // zero samples staged past the end of a series
-constexpr int64_t kGramLMax = 14336;
+constexpr int64_t kGramLMax = 32000;      // longest series of the filtered scan (LDS budget)
+constexpr int64_t kGramLdsXsMax = 14336;  // longer: exact samples read from global memory
 // E groups of the filtered scan (one register list per E of a group; the
 // slot layout needs E_hi + |group| + 1 <= 16 or a shared first chunk).
 constexpr int kGramGroups[6][2] = {{5, 8}, {9, 11}, {12, 13}, {14, 16}, {17, 18}, {19, 20}};
@@ -104,6 +106,7 @@ hipError_t launch_gram_group(const KnnArgs &a, int lo, int hi, int nslots, int64
                              hipStream_t st);
 // Work-list form for the plan: items (row, blk) of filtered group g
 // (kGramGroups[g]), table mode; same outputs as launch_tables_persistent.
+// One workgroup per item (counter, wg_per_cu and n_cu are not used).
 // L_max bounds the rows of the items; a.gram_ld must be >= L_max + kGramPad.
 hipError_t launch_gram_persistent(const KnnArgs &a, int g, const TableItem *items, int n_items,
                                   int *counter, int64_t L_max, int wg_per_cu, int n_cu,

@@ -124,9 +124,11 @@ def test_filtered_knn_bit_exact(edm, ctxs, case):
 
 
 def test_filtered_knn_long_series_sampled(edm, ctxs):
-    # Bench length (5000), long series (12000) and the longest filtered
-    # length (14336): sampled rows vs the oracle.
-    for L, E, seed in ((5000, 20, 0), (5000, 9, 3), (5000, 6, 4), (12000, 13, 1), (14336, 7, 2)):
+    # Bench length (5000), long series (12000), the longest series whose
+    # samples stay in LDS (14336), longer ones read from global memory
+    # (20000) and the longest filtered length (32000): sampled rows vs the oracle.
+    for L, E, seed in ((5000, 20, 0), (5000, 9, 3), (5000, 6, 4), (12000, 13, 1), (14336, 7, 2),
+                       (20000, 9, 5), (32000, 20, 6)):
         X, _, _ = synth.logistic_network(seed=seed, N=4, L=L)
         x = X[2]
         idx, _, w = edm.edm_knn(dev(x), E, 1, 1, want_dist=False, ctx=ctxs["chosen"])
