@@ -417,10 +417,11 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   const int blk0 = bx * kKnnThreads;
   if (blk0 >= m_lo) return;
 
-  const int64_t ld = a.gram_ld;
+  const int64_t ld = a.gram_ld;                            // norm rows
+  const int64_t lds = a.gram_lds > 0 ? a.gram_lds : ld;   // LDS rows (>= L + kGramPad)
   float *xs = smem;  // unused when XG
-  uint16_t *xh = reinterpret_cast<uint16_t *>(XG ? smem : smem + ld);
-  uint16_t *xl = xh + ld;
+  uint16_t *xh = reinterpret_cast<uint16_t *>(XG ? smem : smem + lds);
+  uint16_t *xl = xh + lds;
   // exact samples: LDS copy (zero past L), or the global row with the index
   // clamped to the row (clamped reads only feed keys that are discarded)
   auto xat = [&](int i) -> float {
@@ -429,7 +430,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   };
   const uint32_t *xh32 = reinterpret_cast<const uint32_t *>(xh);
   const uint32_t *xl32 = reinterpret_cast<const uint32_t *>(xl);
-  uint32_t *qbuf_all = reinterpret_cast<uint32_t *>(xl + ld);  // [wave][kQueueCap][64] queues
+  uint32_t *qbuf_all = reinterpret_cast<uint32_t *>(xl + lds);  // [wave][kQueueCap][64] queues
   const float mu = a.gram_mu[row];
   const uint32_t *__restrict__ nrm =
       a.gram_nrm + (static_cast<int64_t>(row) * kGramNE + (ELO - kGramEMin)) * ld;
@@ -1039,12 +1040,13 @@ hipError_t launch_gram_persistent(const KnnArgs &a, int g, const TableItem *item
                            &k_gram_items<12, 13, true>, &k_gram_items<14, 16, true>,
                            &k_gram_items<17, 18, true>, &k_gram_items<19, 20, true>};
   static_assert(sizeof(kGramGroups) / sizeof(kGramGroups[0]) == 6, "one kernel per filtered group");
-  if (g < 0 || g > 5 || L_max > kGramLMax || a.gram_ld < L_max + kGramPad || a.tau != 1 ||
-      a.mom != nullptr)
+  const int64_t lds = a.gram_lds > 0 ? a.gram_lds : a.gram_ld;
+  if (g < 0 || g > 5 || L_max > kGramLMax || a.gram_ld < L_max + kGramPad ||
+      lds < L_max + kGramPad || lds > a.gram_ld || a.tau != 1 || a.mom != nullptr)
     return hipErrorInvalidValue;
-  const bool xg = use_global_x(a.gram_ld - kGramPad);
+  const bool xg = use_global_x(lds - kGramPad);
   const Fn *fns = xg ? fg : fl;
-  const size_t shm = gram_shm(a.gram_ld, xg);
+  const size_t shm = gram_shm(lds, xg);
   const void *fn = reinterpret_cast<const void *>(fns[g]);
   if (shm > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,

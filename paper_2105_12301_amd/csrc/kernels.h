@@ -52,6 +52,7 @@ struct KnnArgs {
   float *gram_mu;
   uint32_t *gram_nrm;
   int64_t gram_ld;
+  int64_t gram_lds;  // LDS row stride of a launch (0: gram_ld); >= its rows' L + kGramPad
   // Sweep mode: when keepE[E] is set, the sorted neighbour list of every
   // query at E is also written there ([slot][m][E+1] int32, slot stride
   // keep_strideE[E]) for a later cross map (launch_tables_from_sweep).

@@ -35,16 +35,18 @@ constexpr int kNGroups = 5;
 constexpr int kGroupLo[kNGroups] = {1, 9, 13, 16, 19};
 constexpr int kGroupHi[kNGroups] = {8, 12, 15, 18, 20};
 constexpr int kNGram = 6;
-constexpr int kNLists = kNGroups + 1 + kNGram;
+// filtered lists come twice: series whose samples fit in LDS, then longer ones
+constexpr int kNLists = kNGroups + 1 + 2 * kNGram;
 
 struct Batch {
-  int64_t L_max = 0, Lg_max = 0;  // longest library; longest filtered library
+  int64_t L_max = 0, Lg_max = 0, Ls_max = 0;  // longest library; longest filtered; longest short filtered
   std::array<int64_t, kNLists> t_begin{}, t_count{};
   std::array<int64_t, EDM_E_MAX + 1> l_begin{}, l_count{}, lds_floats{};
 };
 
-// E range and eligibility of table list c for a library (filtered or not).
-inline bool list_range(int c, bool filt, int &lo, int &hi) {
+// E range and eligibility of table list c for a library (filtered or not;
+// long: more samples than fit in LDS next to the filter's arrays).
+inline bool list_range(int c, bool filt, bool long_, int &lo, int &hi) {
   if (c < kNGroups) {
     lo = kGroupLo[c];
     hi = kGroupHi[c];
@@ -55,9 +57,11 @@ inline bool list_range(int c, bool filt, int &lo, int &hi) {
     hi = edm::kGramEMin - 1;
     return filt;
   }
-  lo = edm::kGramGroups[c - kNGroups - 1][0];
-  hi = edm::kGramGroups[c - kNGroups - 1][1];
-  return filt;
+  const int f = (c - kNGroups - 1) % kNGram;
+  const bool want_long = c - kNGroups - 1 >= kNGram;
+  lo = edm::kGramGroups[f][0];
+  hi = edm::kGramGroups[f][1];
+  return filt && long_ == want_long;
 }
 
 }  // namespace
@@ -208,6 +212,7 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
       const int32_t i = order[static_cast<size_t>(q)];
       B.L_max = std::max(B.L_max, Lx[i]);
       if (filt_of(i)) B.Lg_max = std::max(B.Lg_max, Lx[i]);
+      if (filt_of(i) && Lx[i] <= edm::kGramLdsXsMax) B.Ls_max = std::max(B.Ls_max, Lx[i]);
       for (int E = 1; E <= EDM_E_MAX; ++E) {
         if (!((need[static_cast<size_t>(i)] >> (E - 1)) & 1u)) continue;
         tbl_off[static_cast<size_t>(i) * (EDM_E_MAX + 1) + E] = o;
@@ -222,7 +227,7 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
       for (int64_t q = k0; q < k; ++q) {
         const int32_t i = order[static_cast<size_t>(q)];
         int lo = 0, hi = 0;
-        if (!list_range(c, filt_of(i), lo, hi)) continue;
+        if (!list_range(c, filt_of(i), Lx[i] > edm::kGramLdsXsMax, lo, hi)) continue;
         uint32_t gm = 0;
         for (int E = lo; E <= hi; ++E) gm |= need[static_cast<size_t>(i)] & (1u << (E - 1));
         if (!gm) continue;
@@ -350,11 +355,16 @@ int enqueue_plan(edm_ctx *ctx, edm_plan *P, const float *X, const float *Y, floa
       EDM_HIP(ctx, edm::launch_tables_persistent(a, g, P->titems + B.t_begin[g], static_cast<int>(B.t_count[g]),
                                                  P->counters + c, B.L_max, P->tune.tables_wg_per_cu,
                                                  P->n_cu, st));
-    for (int f = 0; f < kNGram; ++f, ++c) {
-      const int l = kNGroups + 1 + f;
-      EDM_HIP(ctx, edm::launch_gram_persistent(a, f, P->titems + B.t_begin[l], static_cast<int>(B.t_count[l]),
-                                               P->counters + c, B.Lg_max, P->tune.tables_wg_per_cu,
-                                               P->n_cu, st));
+    for (int h = 0; h < 2; ++h) {  // short libraries (LDS stride of the short ones), then long ones
+      edm::KnnArgs ah = a;
+      const int64_t Lh = h == 0 ? B.Ls_max : B.Lg_max;
+      ah.gram_lds = Lh > 0 ? edm::gram_ld(Lh) : 0;
+      for (int f = 0; f < kNGram; ++f, ++c) {
+        const int l = kNGroups + 1 + h * kNGram + f;
+        EDM_HIP(ctx, edm::launch_gram_persistent(ah, f, P->titems + B.t_begin[l], static_cast<int>(B.t_count[l]),
+                                                 P->counters + c, Lh, P->tune.tables_wg_per_cu,
+                                                 P->n_cu, st));
+      }
     }
     edm::LookupArgs b{};
     b.Lx_dev = P->Lx_dev;
