@@ -59,7 +59,7 @@ typedef struct edm_ctx edm_ctx;
  *                   candidate scan per group of E values, extending one
  *                   running key (the key for E is the key for E-1 plus one
  *                   rounded term).
- * EDM_FORM_CHOSEN : EDM_FORM_BATCHED, and for E >= 5 (series up to 14336
+ * EDM_FORM_CHOSEN : EDM_FORM_BATCHED, and for E >= 5 (series up to 32000
  *                   samples) a BF16 matrix-core estimate of every key filters
  *                   the candidates; the ones that may enter a top-k list are
  *                   re-ranked with the exact float32 key.
@@ -120,7 +120,7 @@ int edm_embed(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau,
  *        step 3; when min d = 0 the weights are 1 at zero distance and 0
  *        elsewhere before normalising                               (or NULL)
  * nq = L - (E-1)*tau - Tp.
- * In EDM_FORM_CHOSEN with tau = 1, k = E+1, E >= 5, L <= 14336 and dist ==
+ * In EDM_FORM_CHOSEN with tau = 1, k = E+1, E >= 5, L <= 32000 and dist ==
  * NULL, the table comes from the matrix-core filtered scan (same result). */
 int edm_knn(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau,
             int32_t Tp, int32_t k, int32_t *idx, float *dist, float *w);
@@ -197,6 +197,10 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
  * replayed afterwards (re-captured when the buffers change; a context on the
  * legacy default stream enqueues the launches directly instead, since that
  * stream cannot be captured).  Results equal edm_ccm bit for bit.  tau = 1.
+ * The form is the context's at edm_ccm_plan_create: in EDM_FORM_CHOSEN the
+ * tables of E >= 5 of libraries up to 32000 samples come from the matrix-core
+ * filtered scan (same tables), and the plan holds that filter's norm arrays
+ * for every library (Nl x 16 x ~L_max x 4 bytes).
  * ------------------------------------------------------------------------- */
 typedef struct edm_plan edm_plan;
 
@@ -212,7 +216,8 @@ void edm_tune_default(edm_tune *tune);
 /* Build a plan.  Lx (host) int64 [Nl], Ly (host) int64 [Nt], E_tgt (host)
  * int32 [Nt] in 0..20 (0: no E, the column stays NaN); ldx, ldy the row
  * strides the run will use; tune may be NULL (defaults).  Allocates the
- * plan's device memory (work lists, offsets, one batch of tables). */
+ * plan's device memory (work lists, offsets, one batch of tables and, in the
+ * chosen form, the filter's per-library norms). */
 int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx,
                         const int64_t *Ly, int64_t Nt, int64_t ldy, const int32_t *E_tgt,
                         int32_t Tp, const edm_tune *tune, edm_plan **plan);
