@@ -181,6 +181,25 @@ def test_filtered_sweep_bit_identical(edm, ctxs, family):
     assert np.nanmax(np.abs(g - ro)) <= RHO_TOL
 
 
+def test_filtered_sweep_and_fused_ccm_long_series(edm, ctxs):
+    # Series longer than the LDS copy of the filter (14336 samples): the
+    # exact samples come from global memory; sweep and fused CCM must equal
+    # the plain form bit for bit.
+    X, _, _ = synth.logistic_network(seed=9, N=4, L=16000)
+    lens = np.array([16000, 15000, 14337, 9000])
+    res = _sweep_all(edm, ctxs, X, lens, 20)
+    rp, ep = res["plain"]
+    rc, ec = res["chosen"]
+    assert torch.equal(rp.view(torch.int32), rc.view(torch.int32))
+    assert torch.equal(ep, ec)
+    rho_p = edm.edm_ccm(dev(X), ep, Lx=lens, Ly=lens, Tp=0, ctx=ctxs["plain"])
+    ctxs["plain"].sync()
+    rs, es, rho_c = edm.edm_sweep_ccm(dev(X), lengths=lens, E_max=20, ctx=ctxs["chosen"])
+    ctxs["chosen"].sync()
+    assert torch.equal(rp.view(torch.int32), rs.view(torch.int32))
+    assert torch.equal(rho_p.view(torch.int32), rho_c.view(torch.int32))
+
+
 @pytest.mark.parametrize("E_max", [9, 12, 14, 17])
 def test_filtered_sweep_partial_groups(edm, ctxs, E_max):
     # E_max inside a group: the filtered groups are cut at E_max.
