@@ -1025,13 +1025,9 @@ hipError_t launch_gram_prep(const KnnArgs &a, int nslots, int64_t L_max, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_gram_persistent(const KnnArgs &a, int g, const TableItem *items, int n_items,
-                                  int *counter, int64_t L_max, int wg_per_cu, int n_cu,
-                                  hipStream_t st) {
+hipError_t launch_gram_items(const KnnArgs &a, int g, const TableItem *items, int n_items,
+                             int64_t L_max, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  (void)counter;
-  (void)wg_per_cu;
-  (void)n_cu;
   using Fn = void (*)(KnnArgs, const TableItem *);
   static const Fn fl[6] = {&k_gram_items<5, 8, false>,   &k_gram_items<9, 11, false>,
                            &k_gram_items<12, 13, false>, &k_gram_items<14, 16, false>,

@@ -106,12 +106,11 @@ hipError_t launch_gram_prep(const KnnArgs &a, int nslots, int64_t L_max, hipStre
 hipError_t launch_gram_group(const KnnArgs &a, int lo, int hi, int nslots, int64_t L_max,
                              hipStream_t st);
 // Work-list form for the plan: items (row, blk) of filtered group g
-// (kGramGroups[g]), table mode; same outputs as launch_tables_persistent.
-// One workgroup per item (counter, wg_per_cu and n_cu are not used).
-// L_max bounds the rows of the items; a.gram_ld must be >= L_max + kGramPad.
-hipError_t launch_gram_persistent(const KnnArgs &a, int g, const TableItem *items, int n_items,
-                                  int *counter, int64_t L_max, int wg_per_cu, int n_cu,
-                                  hipStream_t st);
+// (kGramGroups[g]), table mode, one workgroup per item; same outputs as
+// launch_tables_persistent.  L_max bounds the rows of the items; a.gram_ld
+// and the LDS stride a.gram_lds (0: gram_ld) must be >= L_max + kGramPad.
+hipError_t launch_gram_items(const KnnArgs &a, int g, const TableItem *items, int n_items,
+                             int64_t L_max, hipStream_t st);
 
 // Cross-map tables (Tp = 0) of dimension E for `nslots` libraries from the
 // sweep's lists (Tp = 1) in a.keepE[E]; output in a.idxE[E] / a.wE[E] with

@@ -361,9 +361,8 @@ int enqueue_plan(edm_ctx *ctx, edm_plan *P, const float *X, const float *Y, floa
       ah.gram_lds = Lh > 0 ? edm::gram_ld(Lh) : 0;
       for (int f = 0; f < kNGram; ++f, ++c) {
         const int l = kNGroups + 1 + h * kNGram + f;
-        EDM_HIP(ctx, edm::launch_gram_persistent(ah, f, P->titems + B.t_begin[l], static_cast<int>(B.t_count[l]),
-                                                 P->counters + c, Lh, P->tune.tables_wg_per_cu,
-                                                 P->n_cu, st));
+        EDM_HIP(ctx, edm::launch_gram_items(ah, f, P->titems + B.t_begin[l], static_cast<int>(B.t_count[l]),
+                                            Lh, st));
       }
     }
     edm::LookupArgs b{};
