@@ -14,46 +14,47 @@
 // v_mfma_f32_32x32x16_bf16.  Each centred sample is split into two BF16
 // numbers, b = hi + lo + r with |r| <= 2^-16 |b|, and hi*hi' + hi*lo' + lo*hi'
 // (three MFMAs, FP32 accumulation) gives G with an error below
-// 6.1 * 2^-16 |v_p| |v_q| plus the FP32 accumulation error.  The candidate's
-// norm rides along in a spare slot of the contraction (operand value one on
-// the query side), so one instruction chain yields
-//     D = s N_E(q) - 2 G_E(p, q),        s = 1 - 2^-12,
-// and the query side compares D with T = kth_E(p) - s N_E(p).  D <= T is
-// K(p, q) minus a margin 2^-12 (N_E(p) + N_E(q)) (at least three times every
-// rounding above, the canonical key's own rounding and the centring included)
-// compared with the k-th key, so a candidate that fails the test has an exact
-// key above the query's current k-th key and cannot enter its list.  Every
-// candidate that passes ("survivor") is re-ranked with the exact float32 key
-// of Algorithm 1 (lag order, one rounding per operation, contraction off) and
-// offered to the same sorted register lists as the exact scan.  Estimates
-// that are NaN pass (the test is written !(D > T)), and a series with
-// |x - mu| above 2^56 switches the filter off (T = +inf), so the result does
-// not depend on the filter: the tables and correlations are bit-identical to
-// the exact scan's.
+// 6.1 * 2^-16 |v_p| |v_q| plus the FP32 accumulation error.  Two more slots
+// of the contraction finish the test inside the chain: the candidate's norm
+// (operand one on the query side) and the query's threshold (operand one on
+// the candidate side, -T as a BF16 pair rounded down), so one chain yields
+//     e = s N_E(q) - 2 G_E(p, q) - T',   s = 1 - 2^-12,  T' >= T,
+//     T = kth_E(p) - s N_E(p) + 2^-90.
+// e < 0 holds for every candidate whose exact key is at most the query's
+// current k-th key: the slack 2^-12 (N_E(p) + N_E(q)) is at least three times
+// every rounding above (the canonical key's own rounding, the centring and
+// the threshold's rounding included).  A candidate with e >= 0 cannot enter
+// the list.  Every candidate with e < 0 ("survivor") is re-ranked with the
+// exact float32 key of Algorithm 1 (lag order, one rounding per operation,
+// contraction off) and offered to the same sorted register lists as the
+// exact scan, so the tables and correlations are bit-identical to the exact
+// scan's.  |T| is capped at 2^120 (finite operands) and a series with
+// |x - mu| above 2^56 switches the filter off (every candidate survives).
 //
 // Layout on the chip
 // ------------------
-// * Workgroup = 8 waves = the 256 queries of one exact-scan block; the series
-//   is staged in LDS three times: float32 samples (exact re-rank, weights) and
-//   the BF16 hi and lo halves of the centred samples (matrix operands).
+// * Workgroup = 8 waves = the 256 queries of one exact-scan block; LDS holds
+//   the BF16 hi and lo halves of the centred series (matrix operands), the
+//   float32 series (exact re-rank, weights) up to kGramLdsXsMax samples
+//   (beyond, the XG instantiation reads it from global memory), and one
+//   survivor queue per lane.
 // * A wave owns 32 queries.  MFMA operand A holds 32 candidates (tile rows),
-//   operand B the wave's 32 queries (tile columns, fixed for the whole scan),
-//   so lane l ends with the 16 estimates of candidates 8(v/4) + 4(l/32) + v%4
-//   for query l%32: one threshold register per E and lane.  The two lanes of a
-//   query (l and l+32) keep top-k lists over their own half of the
-//   candidates, each in ascending q, and merge them with a lexicographic
-//   (key, index) insertion at the end.
-// * K-slots of the contraction: lags 0..E_hi-1, then one norm slot per E of
-//   the group, then zeros.  A group fits one 16-slot chunk (E_hi + |group| <=
-//   16), or for E >= 16 a shared chunk of lags 0..15 plus one chunk per E.
-// * Two passes over the candidate tiles.  Pass 1 keeps, per lane and value
-//   slot, the candidate with the smallest estimate at E_hi (one hi*hi product
-//   per chunk suffices to rank them); the exact keys
-//   of a query's 32 slot winners give an upper bound of its final k-th key
-//   for every E of the group before any list exists.  Pass 2 filters against
-//   min(bound, current k-th key) and queues the survivors per lane in LDS;
-//   a queue is re-ranked (exact key: E_hi LDS reads and 3 E_hi VALU ops, then
-//   the sorted insertions) only when some lane's queue fills, and at the end.
+//   operand B the wave's 32 queries (tile columns, fixed between threshold
+//   updates), so lane l ends with the 16 estimates of candidates
+//   8(v/4) + 4(l/32) + v%4 for query l%32.  The two lanes of a query (l and
+//   l+32) keep top-k lists over their own half of the candidates, each in
+//   ascending q, merged by a bitonic network at the end.
+// * K-slots: lags 0..E_hi-1, one norm slot per E of the group, the threshold
+//   slot, zeros; a group that does not fit one 16-slot chunk shares a first
+//   chunk of lags 0..S-1 (S = min(E_lo, 16)) and keeps one chunk per E.
+// * Two passes over the candidate tiles.  Pass 1 samples one tile in eight
+//   and keeps, per lane and value slot, the candidate with the smallest
+//   hi*hi estimate at E_hi; the exact keys of a query's 32 slot winners bound
+//   its final k-th key for every E of the group.  Pass 2 tests every tile:
+//   the OR over E of the estimates' sign bits is a per-lane mask, queued with
+//   the tile index in LDS without a branch; the queue is re-ranked when some
+//   lane holds kQueueCap masks, and at the end, and each re-rank refreshes the
+//   thresholds with min(bound, K-th key of the query's two half-lists).
 #include <cstdint>
 #include <type_traits>
 
