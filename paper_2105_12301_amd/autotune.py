@@ -27,11 +27,11 @@ def _cache_path():
                           os.path.join(os.path.expanduser("~"), ".cache", "edm_autotune.json"))
 
 
-def shape_key(Lx, Ly, E):
+def shape_key(Lx, Ly, E, form: int = 0):
     dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
     Lx = np.asarray(Lx)
     return (f"{dev}|Nl~{2 ** int(np.log2(max(len(Lx), 1)))}|Nt~{2 ** int(np.log2(max(len(Ly), 1)))}"
-            f"|Lmax~{int(np.ceil(Lx.max() / 1000))}k|Emax={int(np.max(E))}")
+            f"|Lmax~{int(np.ceil(Lx.max() / 1000))}k|Emax={int(np.max(E))}|form={int(form)}")
 
 
 def make_tune(d) -> edm.Tune:
@@ -43,8 +43,10 @@ def make_tune(d) -> edm.Tune:
 
 def autotune(X, Lx, Y, Ly, E, Tp: int = 0, ctx=None, sample: int = 48, reps: int = 2,
              use_cache: bool = True, log=None):
-    """Return (best Tune, {candidate: ms}) for this workload shape."""
-    key = shape_key(Lx, Ly, E)
+    """Return (best Tune, {candidate: ms}) for this workload shape and the
+    context's form (the chosen form's plan runs other table kernels)."""
+    ctx = ctx or edm.default_context(X.device)
+    key = shape_key(Lx, Ly, E, getattr(ctx, "form", 0))
     path = _cache_path()
     cache = {}
     if use_cache and os.path.exists(path):
@@ -54,7 +56,6 @@ def autotune(X, Lx, Y, Ly, E, Tp: int = 0, ctx=None, sample: int = 48, reps: int
             cache = {}
         if key in cache:
             return make_tune(cache[key]["tune"]), cache[key].get("times", {})
-    ctx = ctx or edm.default_context(X.device)
     Lx = np.asarray(Lx)
     order = np.argsort(-Lx, kind="stable")
     pick = order[np.linspace(0, len(order) - 1, min(sample, len(order))).astype(int)]
