@@ -13,7 +13,6 @@ namespace edm {
 struct Mom;
 
 constexpr int kKnnThreads = 256;  // 4 waves of 64 query points per workgroup
-constexpr int kLookupThreads = 256;
 
 // Arguments of the fused embedding + distance + top-k + weights kernel.
 // One workgroup handles 256 consecutive query points of one library; the

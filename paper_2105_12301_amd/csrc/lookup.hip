@@ -16,8 +16,10 @@
 // Grid kernel: a workgroup stages a tile of T targets of one E (the window
 // [t(0)+Tp, t(nq-1)+Tp] the tables can touch) and its 8 waves run 8
 // libraries' tables against them, each wave reusing every table row for the
-// T targets (8 waves: two workgroups of 64 KB staging fill a CU with 16 waves).  Work-list kernel: one item (library, T <= 16 targets) per
-// workgroup; wave w takes targets 4w .. 4w+3 in one table pass.
+// T targets (8 waves: two workgroups of 64 KB staging fill a CU with 16
+// waves).  Work-list kernel: one item (library, T <= 16 targets, staged in up
+// to 160 KB) per workgroup of 16 waves; wave w takes target w in one table
+// pass.
 #include <array>
 #include <utility>
 
@@ -30,8 +32,10 @@ namespace {
 
 constexpr int kTMax = 8;               // targets per grid workgroup, upper bound
 constexpr int kItemTMax = kLookupItemMaxTargets;
-constexpr int kWaveT = kItemTMax / (kLookupThreads / 64);  // targets per wave in an item
-constexpr int kLookupWaves = kLookupThreads / kWave;
+// Work-list kernel: 16 waves, one target each, so the targets an item stages
+// (up to 160 KB of LDS) keep that many waves busy.
+constexpr int kItemThreads = 1024;
+constexpr int kWaveT = kItemTMax / (kItemThreads / 64);  // targets per wave in an item
 constexpr int kGridWaves = 8;  // libraries per grid workgroup (one wave each)
 constexpr int kGridThreads = kGridWaves * kWave;
 constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS for staged targets
@@ -181,9 +185,9 @@ __global__ __launch_bounds__(kGridThreads) void k_lookup(LookupArgs a, int T, in
 
 // Work-list kernel for one E (K = E + 1): persistent (counter != nullptr:
 // workgroups pull items) or one workgroup per item.  Item fields are made
-// wave-uniform; wave w computes the item's targets 4w .. 4w+3.
+// wave-uniform; wave w computes the item's target w.
 template <int K>
-__global__ __launch_bounds__(kLookupThreads) void k_lookup_items(LookupArgs a,
+__global__ __launch_bounds__(kItemThreads) void k_lookup_items(LookupArgs a,
                                                                 const LookupItem *__restrict__ items,
                                                                 int n_items, int *counter) {
   extern __shared__ float ys[];
@@ -305,12 +309,12 @@ hipError_t launch_lookup_items(const LookupArgs &a, int E, const LookupItem *ite
     if (e != hipSuccess) return e;
   }
   if (wg_per_cu <= 0) {
-    hipLaunchKernelGGL(fns[E - 1], dim3(static_cast<unsigned>(n_items)), dim3(kLookupThreads), shm,
+    hipLaunchKernelGGL(fns[E - 1], dim3(static_cast<unsigned>(n_items)), dim3(kItemThreads), shm,
                        st, a, items, n_items, static_cast<int *>(nullptr));
   } else {
     int grid = wg_per_cu * n_cu;
     if (grid > n_items) grid = n_items;
-    hipLaunchKernelGGL(fns[E - 1], dim3(static_cast<unsigned>(grid)), dim3(kLookupThreads), shm, st,
+    hipLaunchKernelGGL(fns[E - 1], dim3(static_cast<unsigned>(grid)), dim3(kItemThreads), shm, st,
                        a, items, n_items, counter);
   }
   return hipGetLastError();

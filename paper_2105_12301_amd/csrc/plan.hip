@@ -246,7 +246,7 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
         if (!((need[static_cast<size_t>(i)] >> (E - 1)) & 1u)) continue;
         const int64_t cnt = defined(E, Lx[i]);
         const int64_t m = Lx[i] - (E - 1) - Tp;
-        int64_t T = 16384 / m;
+        int64_t T = 40000 / m;  // staged targets of an item: at most 160 KB of LDS
         T = std::max<int64_t>(1, std::min<int64_t>(T, tn.lookup_targets));
         B.lds_floats[E] = std::max(B.lds_floats[E], T * m);
         for (int64_t f = 0; f < cnt; f += T)
