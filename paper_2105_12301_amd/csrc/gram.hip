@@ -81,6 +81,7 @@ constexpr float kGramSafeMax = 0x1p56f;         // larger |x - mu| switches the 
 constexpr int kPass1Gap = 8 * 32;               // pass 1 samples one tile in eight
 constexpr int kQueueCap = 16;                   // queued tile masks per lane before a re-rank
 constexpr float kGramBig = 0x1p120f;            // |threshold| cap: finite BF16 operands
+constexpr int kBufWord3 = 0x00020000;           // raw buffer resource, dword 3 (GFX9 family)
 
 __device__ __forceinline__ uint32_t bf16_bits(float f) {  // round to nearest even (finite f)
   const uint32_t u = __float_as_uint(f);
@@ -423,11 +424,18 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   float *xs = smem;  // unused when XG
   uint16_t *xh = reinterpret_cast<uint16_t *>(XG ? smem : smem + lds);
   uint16_t *xl = xh + lds;
-  // exact samples: LDS copy (zero past L), or the global row with the index
-  // clamped to the row (clamped reads only feed keys that are discarded)
+  // exact samples: LDS copy (zero past L), or the global row through a
+  // buffer resource of L samples (the hardware returns zero past L; those
+  // reads only feed keys that are discarded)
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float *>(x), static_cast<short>(0), L * static_cast<int>(sizeof(float)), kBufWord3);
   auto xat = [&](int i) -> float {
-    if constexpr (XG) return x[i < L ? i : L - 1];
-    else return xs[i];
+    if constexpr (XG) {
+      const int off = i * static_cast<int>(sizeof(float));
+      return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xr, off, 0, 0));
+    } else {
+      return xs[i];
+    }
   };
   const uint32_t *xh32 = reinterpret_cast<const uint32_t *>(xh);
   const uint32_t *xl32 = reinterpret_cast<const uint32_t *>(xl);
