@@ -236,9 +236,11 @@ def main(argv=None):
     form_name = names[main_form]
     if main_form != edm.EDM_FORM_PLAIN:
         ops = batched_sweep_ops(N, L, w["E_max"], w["tau"], w["Tp_sweep"])
-        kernel = ("one batched E sweep (k_sweep_multi groups"
-                  + (" 1-8 + matrix-core filtered k_gram groups 9-20" if main_form == edm.EDM_FORM_CHOSEN else "")
-                  + "): fused embed+distance+top-k+weights+self-lookup; ops counted as the exact batched scan's")
+        groups = ("k_sweep_multi E 1-4 + matrix-core filtered k_gram E groups 5-8, 9-11, 12-13, 14-16, 17-18, 19-20"
+                  if main_form == edm.EDM_FORM_CHOSEN
+                  else "k_sweep_multi E groups 1-8, 9-12, 13-15, 16-18, 19-20")
+        kernel = (f"one batched E sweep ({groups}): fused embed+distance+top-k+weights+self-lookup;"
+                  " ops counted as the exact batched scan's")
     else:
         ops = sweep_ops(N, L, w["E_max"], w["tau"], w["Tp_sweep"])
         kernel = "k_knn (fused embed+distance+top-k+weights+self-lookup), all E of one sweep"
