@@ -66,13 +66,16 @@ struct TableItem {
   int16_t blk;
 };
 
-// Work item of the persistent lookup kernel: a tile of targets of one E for
-// one library (targets bucket_ids[bucket_at[E] + tile*T ...]).
+// Work item of the lookup work-list kernel: a tile of targets of one E
+// (bucket_ids[bucket_at[E] + first ...]) against a group of up to
+// kLookupItemLibs libraries (LookupArgs::item_libs[lib ... lib + nlib - 1],
+// longest first), one wave per library.
 constexpr int kLookupItemMaxTargets = 16;  // T of a LookupItem is at most this
+constexpr int kLookupItemLibs = 16;        // libraries of a LookupItem, at most
 struct LookupItem {
-  int32_t lib;
-  int16_t E;
-  int16_t T;
+  int32_t lib;    // first entry of the item's libraries in item_libs
+  int16_t nlib;   // libraries of the item (1 .. kLookupItemLibs)
+  int16_t T;      // targets staged per tile
   int32_t first;  // index of the tile's first target inside the E bucket
   int32_t count;  // targets in this tile
 };
@@ -154,6 +157,7 @@ struct LookupArgs {
   const float *tbl_w;
   const int32_t *bucket_ids;
   const int32_t *bucket_at;
+  const int32_t *item_libs;  // library ids of the work items' groups
 };
 
 // Lookups of the work list of one E: persistent (wg_per_cu * n_cu

@@ -17,9 +17,10 @@
 // [t(0)+Tp, t(nq-1)+Tp] the tables can touch) and its 8 waves run 8
 // libraries' tables against them, each wave reusing every table row for the
 // T targets (8 waves: two workgroups of 64 KB staging fill a CU with 16
-// waves).  Work-list kernel: one item (library, T <= 16 targets, staged in up
-// to 160 KB) per workgroup of 16 waves; wave w takes target w in one table
-// pass.
+// waves).  Work-list kernel: one item (a group of up to 16 libraries of
+// similar length, T <= 16 targets staged in up to 160 KB) per workgroup of 16
+// waves; wave w runs library w against the staged targets, reusing each table
+// row for up to 4 targets.
 #include <array>
 #include <utility>
 
@@ -32,10 +33,14 @@ namespace {
 
 constexpr int kTMax = 8;               // targets per grid workgroup, upper bound
 constexpr int kItemTMax = kLookupItemMaxTargets;
-// Work-list kernel: 16 waves, one target each, so the targets an item stages
-// (up to 160 KB of LDS) keep that many waves busy.
-constexpr int kItemThreads = 1024;
-constexpr int kWaveT = kItemTMax / (kItemThreads / 64);  // targets per wave in an item
+// Work-list kernel: one wave per library of an item, so every CU keeps 16
+// waves busy however few targets of a long series fit its LDS.
+constexpr int kItemThreads = kLookupItemLibs * 64;
+// targets per table pass of a wave (fewer for the widest rows: registers)
+template <int K>
+constexpr int wave_targets() {
+  return K <= 20 ? 4 : 2;
+}
 constexpr int kGridWaves = 8;  // libraries per grid workgroup (one wave each)
 constexpr int kGridThreads = kGridWaves * kWave;
 constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS for staged targets
@@ -184,64 +189,73 @@ __global__ __launch_bounds__(kGridThreads) void k_lookup(LookupArgs a, int T, in
 }
 
 // Work-list kernel for one E (K = E + 1): persistent (counter != nullptr:
-// workgroups pull items) or one workgroup per item.  Item fields are made
-// wave-uniform; wave w computes the item's target w.
+// workgroups pull items) or one workgroup per item.  An item stages a tile of
+// targets once, over the window of its longest library, and wave w runs the
+// item's library w against every staged target, kWaveT targets per table
+// pass.  Item fields are made wave-uniform.
 template <int K>
 __global__ __launch_bounds__(kItemThreads) void k_lookup_items(LookupArgs a,
                                                                 const LookupItem *__restrict__ items,
                                                                 int n_items, int *counter) {
   extern __shared__ float ys[];
   __shared__ int item_s;
+  __shared__ int tgt[kItemTMax];
+  constexpr int kWaveT = wave_targets<K>();
   const int E = K - 1;
   const int off = (E - 1) * a.tau + a.Tp;
+  const int wave = static_cast<int>(threadIdx.x) / kWave;
   for (int trip = 0;; ++trip) {
     int it;
     if (counter == nullptr) {
       if (trip > 0) break;
       it = static_cast<int>(blockIdx.x);
     } else {
-      __syncthreads();  // the previous item is done with ys and item_s
+      __syncthreads();  // the previous item is done with ys, tgt and item_s
       if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
       __syncthreads();
       it = __builtin_amdgcn_readfirstlane(item_s);
       if (it >= n_items) break;
     }
-    const int lib = __builtin_amdgcn_readfirstlane(items[it].lib);
+    const int at = __builtin_amdgcn_readfirstlane(items[it].lib);
+    const int nlib = __builtin_amdgcn_readfirstlane(static_cast<int>(items[it].nlib));
     const int T = __builtin_amdgcn_readfirstlane(static_cast<int>(items[it].T));
     const int first = __builtin_amdgcn_readfirstlane(items[it].first);
     const int count = __builtin_amdgcn_readfirstlane(items[it].count);
-    const int64_t Lx = a.Lx_dev ? a.Lx_dev[lib] : a.Lx_uni;
-    const int m = static_cast<int>(Lx) - off;
-    const int32_t *ids = a.bucket_ids + a.bucket_at[E];
     const int Tn = count < T ? count : T;
-    int tgt[kItemTMax];
-#pragma unroll
-    for (int t = 0; t < kItemTMax; ++t) tgt[t] = t < Tn ? ids[first + t] : 0;
-    const bool has = m - 1 >= K;  // uniform
-    __syncthreads();  // ys is free
-    if (has) stage_targets(a, tgt, Tn, off, m, m, ys);
+    // the first library of an item is its longest: its window covers all
+    const int lib0 = __builtin_amdgcn_readfirstlane(a.item_libs[at]);
+    const int ms = static_cast<int>((a.Lx_dev ? a.Lx_dev[lib0] : a.Lx_uni) - off);
+    if (static_cast<int>(threadIdx.x) < Tn) tgt[threadIdx.x] = a.bucket_ids[a.bucket_at[E] + first + threadIdx.x];
     __syncthreads();
-    // wave w: targets w*kWaveT .. +kWaveT-1 of the item, one table pass
-    const int wave = static_cast<int>(threadIdx.x) / kWave;
-    const int tw0 = wave * kWaveT;
-    if (has && tw0 < Tn) {  // uniform per wave
-      const int64_t o = a.tbl_off[static_cast<int64_t>(lib) * (EDM_E_MAX + 1) + E];
-      const float *yt[kWaveT];
-      bool ok[kWaveT];
-      float *pred[kWaveT];
+    if (ms >= 1) stage_targets(a, tgt, Tn, off, ms, ms, ys);
+    __syncthreads();
+    if (wave < nlib) {  // uniform per wave
+      const int lib = __builtin_amdgcn_readfirstlane(a.item_libs[at + wave]);
+      const int64_t Lx = a.Lx_dev ? a.Lx_dev[lib] : a.Lx_uni;
+      const int m = static_cast<int>(Lx) - off;
+      if (m - 1 >= K) {
+        const int64_t o = a.tbl_off[static_cast<int64_t>(lib) * (EDM_E_MAX + 1) + E];
+        for (int t0 = 0; t0 < Tn; t0 += kWaveT) {
+          const float *yt[kWaveT];
+          bool ok[kWaveT];
+          float *pred[kWaveT];
+          int id[kWaveT];
 #pragma unroll
-      for (int u = 0; u < kWaveT; ++u) {
-        const int t = tw0 + u;
-        yt[u] = ys + (t < Tn ? t : 0) * m;
-        ok[u] = t < Tn && !(a.Ly_dev && a.Ly_dev[tgt[t]] < Lx);
-        pred[u] = nullptr;
-      }
-      Sums s[kWaveT];
-      wave_pairs<K, kWaveT>(a.tbl_idx + o, a.tbl_w + o, m, yt, ok, pred, s);
-      if (a.rho && (threadIdx.x & (kWave - 1)) == 0) {
+          for (int u = 0; u < kWaveT; ++u) {
+            const int t = t0 + u;
+            id[u] = tgt[t < Tn ? t : 0];
+            yt[u] = ys + (t < Tn ? t : 0) * ms;
+            ok[u] = t < Tn && !(a.Ly_dev && a.Ly_dev[id[u]] < Lx);
+            pred[u] = nullptr;
+          }
+          Sums s[kWaveT];
+          wave_pairs<K, kWaveT>(a.tbl_idx + o, a.tbl_w + o, m, yt, ok, pred, s);
+          if (a.rho && (threadIdx.x & (kWave - 1)) == 0) {
 #pragma unroll
-        for (int u = 0; u < kWaveT; ++u)
-          if (ok[u]) a.rho[static_cast<int64_t>(lib) * a.ldrho + tgt[tw0 + u]] = pair_rho(m, s[u]);
+            for (int u = 0; u < kWaveT; ++u)
+              if (ok[u]) a.rho[static_cast<int64_t>(lib) * a.ldrho + id[u]] = pair_rho(m, s[u]);
+          }
+        }
       }
     }
   }

@@ -81,6 +81,7 @@ struct edm_plan {
   float *tbl_w = nullptr;
   edm::TableItem *titems = nullptr;
   edm::LookupItem *litems = nullptr;
+  int32_t *item_libs = nullptr;
   bool filtered = false;  // some library runs through the matrix-core filter
   int64_t Lg_max = 0, gram_ld = 0;
   float *gram_mu = nullptr;
@@ -188,6 +189,7 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
   std::vector<int64_t> tbl_off(static_cast<size_t>(Nl) * (EDM_E_MAX + 1), 0);
   std::vector<edm::TableItem> titems;
   std::vector<edm::LookupItem> litems;
+  std::vector<int32_t> item_libs;
   int64_t max_batch_elems = 0;
   int64_t k = 0;
   while (k < Nl) {
@@ -238,21 +240,34 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
       }
       B.t_count[c] = static_cast<int64_t>(titems.size()) - B.t_begin[c];
     }
-    // lookup items, per E, longest library first
+    // lookup items, per E: groups of consecutive libraries (longest first)
+    // that need E, each against tiles of the targets its shortest library
+    // pairs with (a prefix of the bucket; a longer library skips the targets
+    // shorter than itself)
     for (int E = 1; E <= EDM_E_MAX; ++E) {
       B.l_begin[E] = static_cast<int64_t>(litems.size());
-      for (int64_t q = k0; q < k; ++q) {
-        const int32_t i = order[static_cast<size_t>(q)];
-        if (!((need[static_cast<size_t>(i)] >> (E - 1)) & 1u)) continue;
-        const int64_t cnt = defined(E, Lx[i]);
-        const int64_t m = Lx[i] - (E - 1) - Tp;
+      std::vector<int32_t> grp;
+      auto close_group = [&]() {
+        if (grp.empty()) return;
+        const int64_t m = Lx[grp.front()] - (E - 1) - Tp;  // the longest window
+        const int64_t cnt = defined(E, Lx[grp.back()]);
         int64_t T = 40000 / m;  // staged targets of an item: at most 160 KB of LDS
         T = std::max<int64_t>(1, std::min<int64_t>(T, tn.lookup_targets));
         B.lds_floats[E] = std::max(B.lds_floats[E], T * m);
+        const int32_t at = static_cast<int32_t>(item_libs.size());
+        item_libs.insert(item_libs.end(), grp.begin(), grp.end());
         for (int64_t f = 0; f < cnt; f += T)
-          litems.push_back(edm::LookupItem{i, static_cast<int16_t>(E), static_cast<int16_t>(T),
+          litems.push_back(edm::LookupItem{at, static_cast<int16_t>(grp.size()), static_cast<int16_t>(T),
                                            static_cast<int32_t>(f), static_cast<int32_t>(std::min(T, cnt - f))});
+        grp.clear();
+      };
+      for (int64_t q = k0; q < k; ++q) {
+        const int32_t i = order[static_cast<size_t>(q)];
+        if (!((need[static_cast<size_t>(i)] >> (E - 1)) & 1u)) continue;
+        grp.push_back(i);
+        if (static_cast<int>(grp.size()) == edm::kLookupItemLibs) close_group();
       }
+      close_group();
       B.l_count[E] = static_cast<int64_t>(litems.size()) - B.l_begin[E];
     }
     P->batches.push_back(B);
@@ -274,6 +289,7 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
   const size_t oCnt = lay.take(sizeof(int) * P->n_counters);
   const size_t oTi = lay.take(sizeof(edm::TableItem) * std::max<size_t>(titems.size(), 1));
   const size_t oLi = lay.take(sizeof(edm::LookupItem) * std::max<size_t>(litems.size(), 1));
+  const size_t oIl = lay.take(sizeof(int32_t) * std::max<size_t>(item_libs.size(), 1));
   const size_t small = lay.bytes;
   const size_t oTidx = lay.take(sizeof(int32_t) * max_batch_elems);
   const size_t oTw = lay.take(sizeof(float) * max_batch_elems);
@@ -296,6 +312,7 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
   P->counters = reinterpret_cast<int *>(P->dev + oCnt);
   P->titems = reinterpret_cast<edm::TableItem *>(P->dev + oTi);
   P->litems = reinterpret_cast<edm::LookupItem *>(P->dev + oLi);
+  P->item_libs = reinterpret_cast<int32_t *>(P->dev + oIl);
   P->tbl_idx = reinterpret_cast<int32_t *>(P->dev + oTidx);
   P->tbl_w = reinterpret_cast<float *>(P->dev + oTw);
   if (P->filtered) {
@@ -311,6 +328,7 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
   std::memcpy(blob.data() + oAt, at.data(), sizeof(int32_t) * at.size());
   if (!titems.empty()) std::memcpy(blob.data() + oTi, titems.data(), sizeof(edm::TableItem) * titems.size());
   if (!litems.empty()) std::memcpy(blob.data() + oLi, litems.data(), sizeof(edm::LookupItem) * litems.size());
+  if (!item_libs.empty()) std::memcpy(blob.data() + oIl, item_libs.data(), sizeof(int32_t) * item_libs.size());
   int rc = upload(ctx, blob.data(), small, P->dev);
   if (rc == EDM_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = set_err(ctx, EDM_E_HIP, "plan upload failed");
   if (rc != EDM_OK) {
@@ -380,6 +398,7 @@ int enqueue_plan(edm_ctx *ctx, edm_plan *P, const float *X, const float *Y, floa
     b.tbl_w = P->tbl_w;
     b.bucket_ids = P->bucket_ids;
     b.bucket_at = P->bucket_at;
+    b.item_libs = P->item_libs;
     for (int E = 1; E <= EDM_E_MAX; ++E, ++c)
       EDM_HIP(ctx, edm::launch_lookup_items(b, E, P->litems + B.l_begin[E], static_cast<int>(B.l_count[E]),
                                             P->counters + c, B.lds_floats[E], P->tune.lookup_wg_per_cu,
