@@ -57,6 +57,33 @@ def test_plan_equals_ccm_bitwise(edm, side, tune, limit, monkeypatch):
         ctx.close()
 
 
+@pytest.mark.parametrize("form", ["plain", "chosen"])
+def test_plan_full_target_tiles_bitwise(edm, side, form):
+    # Few E values, so each E bucket holds ~20 targets: lookup items stage 16
+    # targets, every wave makes several table passes (4 targets a pass, 2 at
+    # E = 20), and each group of 16 libraries of mixed length skips the
+    # targets shorter than a library.
+    from paper_2105_12301_amd.autotune import make_tune
+    X, lens, _ = synth.spike_trains(seed=24, N=64, L_min=150, L_max=1400)
+    E = np.random.default_rng(24).choice(np.array([3, 6, 20], np.int32), size=len(lens))
+    with torch.cuda.stream(side):
+        ctx = edm.Context(device=0, stream=side, form=edm.EDM_FORM_PLAIN)
+        Xd = dev(X)
+        ref = edm.edm_ccm(Xd, dev(E), Lx=lens, Ly=lens, ctx=ctx)
+        if form == "chosen":
+            ctx.set_form(edm.EDM_FORM_CHOSEN)
+        tune = make_tune(dict(tables_wg_per_cu=0, lookup_wg_per_cu=4, lookup_targets=16))
+        plan = edm.CcmPlan(lens, lens, E, X.shape[1], X.shape[1], tune=tune, ctx=ctx)
+        r1 = plan.run(Xd).clone()
+        r2 = plan.run(Xd).clone()
+        ctx.sync()
+        assert torch.isfinite(ref).sum().item() > 1000
+        assert torch.equal(ref.view(torch.int32), r1.view(torch.int32))
+        assert torch.equal(r1.view(torch.int32), r2.view(torch.int32))
+        plan.close()
+        ctx.close()
+
+
 @pytest.mark.parametrize("tune", TUNES[:2], ids=["grid", "persistent-1"])
 def test_chosen_plan_equals_plain_ccm_bitwise(edm, side, tune):
     # In the chosen form the plan's tables for E >= 5 come from the matrix-core
