@@ -191,8 +191,9 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
  * libraries are ordered longest first and split into batches that fit the
  * workspace limit; per batch, one persistent kernel per E group builds every
  * table the library's targets need (one candidate scan per group, as the
- * chosen form of edm_ccm) and one persistent kernel per E runs the lookups.
- * Work items are pulled from device counters, longest first.  The whole
+ * chosen form of edm_ccm) and one persistent kernel per E runs the lookups,
+ * each lookup item a group of up to 16 libraries against one staged tile of
+ * targets.  Work items are pulled from device counters, longest first.  The whole
  * sequence is captured into a HIP graph on the first edm_ccm_plan_run and
  * replayed afterwards (re-captured when the buffers change; a context on the
  * legacy default stream enqueues the launches directly instead, since that
@@ -208,7 +209,8 @@ typedef struct edm_plan edm_plan;
 typedef struct {
   int32_t tables_wg_per_cu;   /* 0: one workgroup per table item; >0: persistent workgroups per CU */
   int32_t lookup_wg_per_cu;   /* 0: one workgroup per lookup item; >0: persistent workgroups per CU */
-  int32_t lookup_targets;     /* targets staged per lookup workgroup, 1..16 */
+  int32_t lookup_targets;     /* targets staged per lookup item, 1..16 (fewer where the
+                                 longest library's window would pass 160 KB of LDS) */
 } edm_tune;
 
 void edm_tune_default(edm_tune *tune);
