@@ -288,3 +288,89 @@ def test_logistic_one_way_causality():
     # unrelated pairs carry no skill
     off = [(a, b) for a in range(8) for b in range(8) if a // 2 != b // 2]
     assert max(abs(rho[a, b]) for a, b in off) < 0.2
+
+
+def _hand_weights(x, p, nbrs, E, tau):
+    # Section 2.1 step 3 written out in Python doubles: Euclidean distances
+    # of the float32 samples, w = exp(-d / d_min) (the limit 1/0 when d_min
+    # is 0), normalised.
+    d = [math.sqrt(sum((float(x[p + j * tau]) - float(x[q + j * tau])) ** 2 for j in range(E)))
+         for q in nbrs]
+    dmin = min(d)
+    w = [math.exp(-di / dmin) for di in d] if dmin > 0 else [1.0 if di == 0 else 0.0 for di in d]
+    s = sum(w)
+    return d, [wi / s for wi in w]
+
+
+def _hand_pearson(a, b):
+    n = len(a)
+    ma, mb = sum(a) / n, sum(b) / n
+    sab = sum((u - ma) * (v - mb) for u, v in zip(a, b))
+    saa = sum((u - ma) ** 2 for u in a)
+    sbb = sum((v - mb) ** 2 for v in b)
+    return sab / math.sqrt(saa * sbb)
+
+
+def _hand_rho(x, y, E, tau, Tp):
+    """rho of one (library x, target y) pair through brute_knn, hand weights,
+    the first-component lookup and a two-pass Pearson (Section 2.1 steps 1-4)."""
+    idx, _ = brute_knn(x, E, tau, Tp, E + 1)
+    off = (E - 1) * tau + Tp
+    yhat, obs = [], []
+    for p, nbrs in enumerate(idx):
+        _, w = _hand_weights(x, p, nbrs, E, tau)
+        yhat.append(sum(wi * float(y[q + off]) for wi, q in zip(w, nbrs)))
+        obs.append(float(y[p + off]))
+    return _hand_pearson(obs, yhat)
+
+
+def test_ccm_embeds_library_at_target_E():
+    # Section 3.4: the pair (library i, target j) uses the target's optimal E.
+    # Uneven E_tgt (1, 4, 7) and libraries of uneven length; each rho is
+    # recomputed through the brute-force path at E_tgt[j].  Using the
+    # library's own E instead changes several pairs by far more than the
+    # tolerance, which the second half checks.
+    rng = np.random.default_rng(11)
+    L = np.array([52, 48, 60])
+    X = np.zeros((3, 60), dtype=np.float32)
+    X[0] = synth.sine(60, period=9.7)
+    X[1] = rng.normal(size=60).astype(np.float32)
+    X[2] = (np.cumsum(rng.normal(size=60)) * 0.1).astype(np.float32)
+    E_tgt = np.array([1, 4, 7])
+    rho = O.ccm(X, L, X, L, E_tgt, tau=1, Tp=0)
+    lib_e = np.zeros((3, 3))
+    for i in range(3):
+        for j in range(3):
+            if L[j] < L[i]:
+                assert np.isnan(rho[i, j])
+                continue
+            x = X[i, :L[i]]
+            y = X[j, :L[i]]
+            want = _hand_rho(x, y, int(E_tgt[j]), 1, 0)
+            assert abs(rho[i, j] - want) < 1e-12, (i, j)
+            lib_e[i, j] = abs(_hand_rho(x, y, int(E_tgt[i]), 1, 0) - want)
+    assert np.sum(lib_e > 1e-3) >= 3
+
+
+def test_knn_rows_beyond_one_block_noncontiguous():
+    # Rows spanning two 512-row blocks of knn_rows, chosen non-contiguously
+    # from a 1100-point series, against brute force on those rows; weights
+    # of the same rows through weights(rows=) against the hand formula.
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=1100).astype(np.float32)
+    E, tau, Tp = 2, 1, 1
+    m = 1100 - (E - 1) * tau - Tp
+    rows = np.sort(rng.choice(m, size=700, replace=False))
+    idx, key = O.knn_rows(x, E, tau, Tp, rows)
+    assert idx.shape == (700, E + 1)
+    _, W = O.weights(x, idx, E, tau, rows=rows)
+    for r in (0, 1, 255, 510, 511, 512, 513, 640, 698, 699):
+        p = int(rows[r])
+        cand = sorted((brute_key(x, p, q, E, tau), q) for q in range(m) if q != p)[:E + 1]
+        assert idx[r].tolist() == [q for _, q in cand], r
+        assert key[r].tolist() == [k for k, _ in cand], r
+        _, w = _hand_weights(x, p, [q for _, q in cand], E, tau)
+        np.testing.assert_allclose(W[r], w, rtol=1e-13, atol=0)
+    # a smaller block size gives the same rows
+    idx2, key2 = O.knn_rows(x, E, tau, Tp, rows, block=97)
+    np.testing.assert_array_equal(idx2, idx)
