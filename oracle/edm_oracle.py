@@ -36,7 +36,10 @@ notes):
 * Horizon Tp: queries and candidate neighbours are both p in [0, n - Tp), with
   n = L - (E-1)*tau, so every neighbour's future value Y[t(q) + Tp] exists.
   The observation at query p is O(p) = Y[t(p) + Tp].
-* Self exclusion: q = p is never a neighbour; no wider exclusion window.
+* Self exclusion: q = p is never a neighbour.  An optional exclusion radius
+  r >= 0 (a Theiler window, which the paper does not use; default 0) also
+  removes every candidate with |q - p| <= r; a call needs at least k
+  candidates for every query, m - 1 - 2 r >= k.
 * Ranking uses the float32 squared key; ties are broken by the lower index q.
 * Weights: d_min = min_i D_i over all k neighbours.  When d_min = 0 the exact
   limit of exp(-D_i/d_min) is used: weight 1 where D_i = 0, else 0.
@@ -103,34 +106,36 @@ def knn_keys(x, E: int, tau: int, Tp: int, rows=None) -> np.ndarray:
     return acc
 
 
-def knn(x, E: int, tau: int, Tp: int, k: int = 0, block: int = 512):
+def knn(x, E: int, tau: int, Tp: int, k: int = 0, block: int = 512, excl: int = 0):
     """All k-nearest-neighbour table of one library, Section 2.1 step 2.
 
-    For every query p in [0, n - Tp): the k candidates q in [0, n - Tp), q != p,
-    with the smallest (key, q), in ascending order (Algorithm 2's result).
-    k = 0 means k = E + 1.  Returns (idx int32 [nq][k], key float32 [nq][k]).
+    For every query p in [0, n - Tp): the k candidates q in [0, n - Tp) with
+    |q - p| > excl (excl = 0: q != p) and the smallest (key, q), in ascending
+    order (Algorithm 2's result).  k = 0 means k = E + 1.  Returns
+    (idx int32 [nq][k], key float32 [nq][k]).
     """
     n = n_embedded(len(x), E, tau)
-    return knn_rows(x, E, tau, Tp, np.arange(max(n - Tp, 0)), k, block)
+    return knn_rows(x, E, tau, Tp, np.arange(max(n - Tp, 0)), k, block, excl)
 
 
-def knn_rows(x, E: int, tau: int, Tp: int, rows, k: int = 0, block: int = 512):
+def knn_rows(x, E: int, tau: int, Tp: int, rows, k: int = 0, block: int = 512, excl: int = 0):
     """The rows ``rows`` of the table of ``knn`` (same definition), for
     checking sampled query points of long series."""
     if k == 0:
         k = E + 1
     n = n_embedded(len(x), E, tau)
     m = n - Tp
-    if E < 1 or tau < 1 or Tp < 0 or k < 1 or m - 1 < k:
+    if E < 1 or tau < 1 or Tp < 0 or k < 1 or excl < 0 or m - 1 - 2 * excl < k:
         raise ValueError("not enough points for k neighbours")
     rows = np.asarray(rows, dtype=np.int64)
     idx = np.empty((rows.size, k), dtype=np.int32)
     key = np.empty((rows.size, k), dtype=np.float32)
+    allq = np.arange(m)
     for b0 in range(0, rows.size, block):
         blk = rows[b0:b0 + block]
         K = knn_keys(x, E, tau, Tp, blk)
         for r, p in enumerate(blk):
-            cand = np.delete(np.arange(m), p)           # self excluded
+            cand = allq[np.abs(allq - p) > excl]         # self (and its window) excluded
             ck = K[r, cand]
             order = np.argsort(ck, kind="stable")[:k]   # ties keep lower q first
             idx[b0 + r] = cand[order]
@@ -191,16 +196,16 @@ def pearson(a, b) -> float:
     return float((da * db).sum() / np.sqrt((da * da).sum() * (db * db).sum()))
 
 
-def simplex_rho(x, y, E: int, tau: int, Tp: int, k: int = 0) -> float:
+def simplex_rho(x, y, E: int, tau: int, Tp: int, k: int = 0, excl: int = 0) -> float:
     """rho of predicting target y from library x (steps 1-4 for one pair)."""
-    idx, _ = knn(x, E, tau, Tp, k)
+    idx, _ = knn(x, E, tau, Tp, k, excl=excl)
     _, wbar = weights(x, idx, E, tau)
     yhat, obs = lookup(idx, wbar, y, E, tau, Tp)
     return pearson(obs, yhat)
 
 
-def _feasible(L: int, E: int, tau: int, Tp: int, k: int) -> bool:
-    return n_embedded(L, E, tau) - Tp - 1 >= k
+def _feasible(L: int, E: int, tau: int, Tp: int, k: int, excl: int = 0) -> bool:
+    return n_embedded(L, E, tau) - Tp - 1 - 2 * excl >= k
 
 
 def select_E(rho_row) -> int:
@@ -212,7 +217,7 @@ def select_E(rho_row) -> int:
     return best_e
 
 
-def simplex_sweep(X, lengths, E_max: int, tau: int = 1, Tp: int = 1):
+def simplex_sweep(X, lengths, E_max: int, tau: int = 1, Tp: int = 1, excl: int = 0):
     """Simplex E sweep: each series predicts itself Tp steps ahead.
 
     For E = 1..E_max the library and the target are the same series (Section
@@ -228,14 +233,14 @@ def simplex_sweep(X, lengths, E_max: int, tau: int = 1, Tp: int = 1):
         L = int(lengths[s])
         x = X[s, :L]
         for E in range(1, E_max + 1):
-            if _feasible(L, E, tau, Tp, E + 1):
-                rho[s, E - 1] = simplex_rho(x, x, E, tau, Tp)
+            if _feasible(L, E, tau, Tp, E + 1, excl):
+                rho[s, E - 1] = simplex_rho(x, x, E, tau, Tp, excl=excl)
         E_opt[s] = select_E(rho[s])
     return rho, E_opt
 
 
 def ccm(X, Lx, Y, Ly, E_tgt, tau: int = 1, Tp: int = 0, lib_rows=None,
-        tgt_cols=None):
+        tgt_cols=None, excl: int = 0):
     """All-to-all CCM, Section 2.1 (pairwise) and Section 3.4.
 
     rho[i][j] is the skill of predicting target Y_j from library X_i embedded
@@ -254,10 +259,10 @@ def ccm(X, Lx, Y, Ly, E_tgt, tau: int = 1, Tp: int = 0, lib_rows=None,
         tables = {}
         for b, j in enumerate(tgt_cols):
             E = int(E_tgt[j])
-            if E < 1 or int(Ly[j]) < L or not _feasible(L, E, tau, Tp, E + 1):
+            if E < 1 or int(Ly[j]) < L or not _feasible(L, E, tau, Tp, E + 1, excl):
                 continue
             if E not in tables:
-                idx, _ = knn(x, E, tau, Tp)
+                idx, _ = knn(x, E, tau, Tp, excl=excl)
                 _, wbar = weights(x, idx, E, tau)
                 tables[E] = (idx, wbar)
             idx, wbar = tables[E]

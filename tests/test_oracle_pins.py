@@ -374,3 +374,49 @@ def test_knn_rows_beyond_one_block_noncontiguous():
     # a smaller block size gives the same rows
     idx2, key2 = O.knn_rows(x, E, tau, Tp, rows, block=97)
     np.testing.assert_array_equal(idx2, idx)
+
+
+def brute_knn_excl(x, E, tau, Tp, k, excl):
+    n = len(x) - (E - 1) * tau
+    m = n - Tp
+    out = []
+    for p in range(m):
+        cand = sorted((brute_key(x, p, q, E, tau), q) for q in range(m) if abs(q - p) > excl)
+        out.append([q for _, q in cand[:k]])
+    return np.array(out)
+
+
+@pytest.mark.parametrize("excl", [0, 1, 3, 5])
+def test_exclusion_radius_ramp_closed_form(excl):
+    # X[t] = t: the key is E (p - q)^2, so with radius r an interior point's
+    # neighbours start at p -/+ (r + 1), lower index first on equal keys, and
+    # are one-sided near the ends.
+    x = synth.ramp(40)
+    idx, key = O.knn(x, 1, 1, 0, excl=excl)   # k = 2
+    p = 20
+    assert idx[p].tolist() == [p - excl - 1, p + excl + 1]
+    assert key[p].tolist() == [float((excl + 1) ** 2)] * 2
+    assert idx[0].tolist() == [excl + 1, excl + 2]
+    assert idx[39].tolist() == [39 - excl - 1, 39 - excl - 2]
+    idx, _ = O.knn(x, 2, 1, 1, excl=excl)     # k = 3, n = 39, queries [0, 38)
+    assert idx[p].tolist() == [p - excl - 1, p + excl + 1, p - excl - 2]
+    assert np.all(np.abs(idx - np.arange(idx.shape[0])[:, None]) > excl)
+
+
+@pytest.mark.parametrize("excl", [1, 4])
+@pytest.mark.parametrize("E,tau,Tp", [(1, 1, 0), (3, 1, 1), (2, 2, 1)])
+def test_exclusion_radius_matches_bruteforce(excl, E, tau, Tp):
+    x = tiny_series(5, 48, dup=True)
+    idx, _ = O.knn(x, E, tau, Tp, excl=excl)
+    np.testing.assert_array_equal(idx, brute_knn_excl(x, E, tau, Tp, E + 1, excl))
+
+
+def test_exclusion_radius_feasibility():
+    # L = 20, Tp = 1, radius 2: a query needs m - 1 - 2r >= E + 1 candidates,
+    # 20 - (E - 1) - 1 - 1 - 4 >= E + 1, i.e. E <= 7.
+    x = np.random.default_rng(9).normal(size=(1, 20)).astype(np.float32)
+    rho, _ = O.simplex_sweep(x, [20], 9, excl=2)
+    assert np.all(np.isfinite(rho[0, :7])) and np.all(np.isnan(rho[0, 7:]))
+    with pytest.raises(ValueError):
+        O.knn(x[0], 8, 1, 1, excl=2)
+    O.knn(x[0], 7, 1, 1, excl=2)
