@@ -104,6 +104,39 @@ const char *edm_last_error(const edm_ctx *ctx);
 /* Release the workspace and the context.  Synchronises its stream first. */
 void edm_ctx_destroy(edm_ctx *ctx);
 
+/* ---------------------------------------------------------------------------
+ * Kernel timing.  With timing on, every call on the context records a pair
+ * of HIP events on its stream around each kernel launch and attributes the
+ * time to one kernel family.  Launches inside a captured plan graph are not
+ * timed.  Timing adds two event records per launch; it is off by default.
+ * ------------------------------------------------------------------------- */
+enum {
+  EDM_KF_EXACT_SCAN = 0,        /* k_knn: one candidate scan per (library, E)        */
+  EDM_KF_BATCHED_SCAN = 1,      /* k_sweep_multi, k_tables_persistent: exact scans
+                                   of groups of E values                            */
+  EDM_KF_FILTER_PREP = 2,       /* k_gram_mean, k_gram_norms                         */
+  EDM_KF_FILTER_SCAN = 3,       /* k_gram, k_gram_items: matrix-core filtered scans  */
+  EDM_KF_TABLES_FROM_SWEEP = 4, /* k_fix_from_sweep, k_scan_queries                  */
+  EDM_KF_LOOKUP = 5,            /* k_lookup, k_lookup_items                          */
+  EDM_KF_FINALIZE = 6,          /* k_sweep_finalize                                  */
+  EDM_KF_OTHER = 7,             /* fills, embedding, candidate sets, network         */
+  EDM_KF_DISTANCES = 8,         /* two-kernel form: distance matrix (Algorithm 1)    */
+  EDM_KF_ROW_TOPK = 9,          /* two-kernel form: per-row top-k (Algorithm 2)      */
+  EDM_KF_GROUP = 10,            /* grouping of targets by E on the device            */
+  EDM_KF_PLAN = 11,             /* one replay of a batched plan's graph, as a whole  */
+  EDM_KF_COUNT = 12
+};
+
+/* Switch timing on (on != 0) or off; either way the accumulated times are
+ * cleared. */
+int edm_ctx_set_timing(edm_ctx *ctx, int on);
+
+/* Wait for the context's stream, then add the time (milliseconds) and the
+ * number of launches recorded per family since the last call (or since
+ * edm_ctx_set_timing) into ms[EDM_KF_COUNT] and launches[EDM_KF_COUNT]
+ * (host arrays; either may be NULL) and clear the records. */
+int edm_ctx_timing(edm_ctx *ctx, double *ms, int64_t *launches);
+
 /* Time-delay embedding, Section 2.1 step 1.
  * x   : float32 [L]
  * out : float32 [n][E], n = L - (E-1)*tau, out[p][j] = x[p + j*tau]. */

@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/edm.h"
 
@@ -21,6 +23,14 @@ struct edm_ctx {
   size_t pinned_bytes = 0;
   hipEvent_t pinned_ready = nullptr;  // recorded after the last copy out of `pinned`
   bool pinned_pending = false;
+  // kernel timing (edm_ctx_set_timing): event pairs recorded around launches
+  bool timing = false;
+  struct TimedRange {
+    int family;
+    hipEvent_t start, stop;
+  };
+  std::vector<TimedRange> ranges;
+  std::vector<hipEvent_t> spare_events;
 };
 
 namespace edm {
@@ -33,6 +43,14 @@ size_t workspace_limit();
 int ws_reserve(edm_ctx *ctx, size_t bytes);
 int upload(edm_ctx *ctx, const void *host, size_t bytes, void *dev);
 int check_ctx(edm_ctx *ctx);
+
+// While alive, kernel launches of this thread are timed on ctx (when its
+// timing is on); one of these opens every C ABI call that launches kernels.
+struct TimingScope {
+  explicit TimingScope(edm_ctx *ctx);
+  ~TimingScope();
+  edm_ctx *prev;
+};
 
 // Sub-allocation plan inside a buffer.
 struct Plan {

@@ -107,6 +107,63 @@ int check_ctx(edm_ctx *ctx) {
   return EDM_OK;
 }
 
+namespace {
+thread_local edm_ctx *g_timed = nullptr;  // context whose launches are being timed
+
+hipEvent_t take_event(edm_ctx *ctx) {
+  if (!ctx->spare_events.empty()) {
+    hipEvent_t e = ctx->spare_events.back();
+    ctx->spare_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+void drop_ranges(edm_ctx *ctx) {
+  for (auto &r : ctx->ranges) {
+    ctx->spare_events.push_back(r.start);
+    ctx->spare_events.push_back(r.stop);
+  }
+  ctx->ranges.clear();
+}
+}  // namespace
+
+TimingScope::TimingScope(edm_ctx *ctx) : prev(g_timed) { g_timed = (ctx && ctx->timing) ? ctx : nullptr; }
+TimingScope::~TimingScope() { g_timed = prev; }
+
+}  // namespace host
+
+TimedLaunch::TimedLaunch(int fam, hipStream_t s) : family(fam), st(s) {
+  edm_ctx *ctx = host::g_timed;
+  if (!ctx) return;
+  start = host::take_event(ctx);
+  if (start && hipEventRecord(start, st) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->spare_events.push_back(start);
+    start = nullptr;
+  }
+}
+
+TimedLaunch::~TimedLaunch() {
+  edm_ctx *ctx = host::g_timed;
+  if (!ctx || !start) return;
+  hipEvent_t stop = host::take_event(ctx);
+  if (!stop || hipEventRecord(stop, st) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->spare_events.push_back(start);
+    if (stop) ctx->spare_events.push_back(stop);
+    return;
+  }
+  ctx->ranges.push_back(edm_ctx::TimedRange{family, start, stop});
+}
+
+namespace host {
+
 
 }  // namespace host
 }  // namespace edm
@@ -161,9 +218,39 @@ int edm_sync(edm_ctx *ctx) {
 
 const char *edm_last_error(const edm_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
 
+int edm_ctx_set_timing(edm_ctx *ctx, int on) {
+  EDM_RC(check_ctx(ctx));
+  EDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  drop_ranges(ctx);
+  ctx->timing = on != 0;
+  return EDM_OK;
+}
+
+int edm_ctx_timing(edm_ctx *ctx, double *ms, int64_t *launches) {
+  EDM_RC(check_ctx(ctx));
+  EDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (const auto &r : ctx->ranges) {
+    float t = 0.0f;
+    const hipError_t e = hipEventElapsedTime(&t, r.start, r.stop);
+    if (e != hipSuccess) {
+      drop_ranges(ctx);
+      return hip_err(ctx, e, "hipEventElapsedTime");
+    }
+    if (r.family >= 0 && r.family < EDM_KF_COUNT) {
+      if (ms) ms[r.family] += t;
+      if (launches) launches[r.family] += 1;
+    }
+  }
+  drop_ranges(ctx);
+  return EDM_OK;
+}
+
 void edm_ctx_destroy(edm_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
+  drop_ranges(ctx);
+  for (hipEvent_t e : ctx->spare_events) (void)hipEventDestroy(e);
+  ctx->spare_events.clear();
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->status) (void)hipFree(ctx->status);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -172,6 +259,7 @@ void edm_ctx_destroy(edm_ctx *ctx) {
 }
 
 int edm_embed(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau, float *out) {
+  TimingScope timing_scope(ctx);
   std::string msg;
   const int rc = edm::check_embed(x, L, E, tau, out, msg);
   if (rc != EDM_OK) return set_err(ctx, rc, msg);
@@ -182,6 +270,7 @@ int edm_embed(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau, f
 
 int edm_knn(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau, int32_t Tp,
             int32_t k, int32_t *idx, float *dist, float *w) {
+  TimingScope timing_scope(ctx);
   std::string msg;
   const int rc = edm::check_knn(x, L, E, tau, Tp, k, idx, msg);
   if (rc != EDM_OK) return set_err(ctx, rc, msg);
@@ -239,6 +328,7 @@ int edm_knn(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau, int
 int edm_lookup(edm_ctx *ctx, const int32_t *idx, const float *w, int64_t nq, int32_t k, int32_t E,
                int32_t tau, int32_t Tp, const float *Y, int64_t N, int64_t ldy, float *pred,
                float *rho) {
+  TimingScope timing_scope(ctx);
   std::string msg;
   const int rc = edm::check_lookup(idx, w, nq, k, E, tau, Tp, Y, N, ldy, pred, rho, msg);
   if (rc != EDM_OK) return set_err(ctx, rc, msg);
@@ -271,6 +361,7 @@ int edm_lookup(edm_ctx *ctx, const int32_t *idx, const float *w, int64_t nq, int
 
 int edm_simplex_sweep(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int64_t ldx,
                       int32_t E_max, int32_t tau, int32_t Tp, float *rho, int32_t *E_opt) {
+  TimingScope timing_scope(ctx);
   std::string msg;
   const int rc = edm::check_sweep(X, L, N, ldx, E_max, tau, Tp, rho, E_opt, msg);
   if (rc != EDM_OK) return set_err(ctx, rc, msg);
@@ -353,6 +444,7 @@ int edm_simplex_sweep(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N,
 
 int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int64_t ldx,
                   int32_t E_max, int32_t tau, float *rho_sweep, int32_t *E_opt, float *rho) {
+  TimingScope timing_scope(ctx);
   std::string msg;
   const int rc = edm::check_sweep(X, L, N, ldx, E_max, tau, 1, rho_sweep, E_opt, msg);
   if (rc != EDM_OK) return set_err(ctx, rc, msg);
@@ -487,6 +579,7 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
 int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t ldx,
             const float *Y, const int64_t *Ly, int64_t Nt, int64_t ldy, const int32_t *E_tgt,
             int32_t tau, int32_t Tp, float *rho) {
+  TimingScope timing_scope(ctx);
   std::string msg;
   const int rc = edm::check_ccm(X, Lx, Nl, ldx, Y, Ly, Nt, ldy, E_tgt, tau, Tp, rho, msg);
   if (rc != EDM_OK) return set_err(ctx, rc, msg);
@@ -701,6 +794,7 @@ int net_ws(edm_ctx *ctx, int32_t C, int64_t B, int64_t L) {
 
 int edm_net_forward(edm_ctx *ctx, const float *params, int32_t C, const float *X, int64_t B,
                     int64_t L, int64_t ldx, float *logits) {
+  TimingScope timing_scope(ctx);
   EDM_RC(check_net(ctx, params, C, X, B, L, ldx));
   if (B > 0 && !logits) return set_err(ctx, EDM_E_ARG, "NULL logits");
   EDM_RC(check_ctx(ctx));
@@ -712,6 +806,7 @@ int edm_net_forward(edm_ctx *ctx, const float *params, int32_t C, const float *X
 
 int edm_net_forward_bf16(edm_ctx *ctx, const float *params, int32_t C, const float *X, int64_t B,
                          int64_t L, int64_t ldx, float *logits) {
+  TimingScope timing_scope(ctx);
   EDM_RC(check_net(ctx, params, C, X, B, L, ldx));
   if (C != 32 && C != 64) return set_err(ctx, EDM_E_ARG, "the BF16 forward needs C = 32 or 64");
   if (B > 0 && !logits) return set_err(ctx, EDM_E_ARG, "NULL logits");
@@ -725,6 +820,7 @@ int edm_net_forward_bf16(edm_ctx *ctx, const float *params, int32_t C, const flo
 int edm_net_loss_grad(edm_ctx *ctx, const float *params, int32_t C, const float *X,
                       const int32_t *labels, int64_t B, int64_t L, int64_t ldx, float *loss,
                       float *grad) {
+  TimingScope timing_scope(ctx);
   EDM_RC(check_net(ctx, params, C, X, B, L, ldx));
   if (B < 1 || !labels || !loss || !grad) return set_err(ctx, EDM_E_ARG, "need B >= 1 and labels, loss, grad");
   EDM_RC(check_ctx(ctx));
@@ -735,6 +831,7 @@ int edm_net_loss_grad(edm_ctx *ctx, const float *params, int32_t C, const float 
 
 int edm_net_adam(edm_ctx *ctx, float *params, const float *grad, float *m, float *v, int64_t n,
                  int32_t step, float lr, float beta1, float beta2, float eps) {
+  TimingScope timing_scope(ctx);
   if (!params || !grad || !m || !v) return set_err(ctx, EDM_E_ARG, "NULL pointer");
   if (n < 0 || step < 1) return set_err(ctx, EDM_E_ARG, "need n >= 0 and step >= 1");
   if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps >= 0.0f))
@@ -748,6 +845,7 @@ int edm_net_adam(edm_ctx *ctx, float *params, const float *grad, float *m, float
 int edm_select_E(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int64_t ldx,
                  int32_t E_max, int32_t tau, int32_t Tp, const float *logits, int32_t m_top,
                  float min_conf, float *rho, int32_t *E_opt, int64_t *n_fallback) {
+  TimingScope timing_scope(ctx);
   std::string msg;
   const int rc = edm::check_sweep(X, L, N, ldx, E_max, tau, Tp, rho, E_opt, msg);
   if (rc != EDM_OK) return set_err(ctx, rc, msg);

@@ -176,6 +176,7 @@ hipError_t launch_tables_from_sweep(const KnnArgs &a, int E, int nslots, int64_t
       !a.wE[E])
     return hipErrorInvalidValue;
   if (nslots <= 0) return hipSuccess;
+  TimedLaunch timed(EDM_KF_TABLES_FROM_SWEEP, st);
   return t[E - 1](a, nslots, L_max, st);
 }
 

@@ -1026,6 +1026,7 @@ size_t gram_shm(int64_t ld, bool xg) {
 hipError_t launch_gram_prep(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t st) {
   if (nslots <= 0) return hipSuccess;
   if (a.gram_ld < L_max + kGramPad) return hipErrorInvalidValue;
+  TimedLaunch timed(EDM_KF_FILTER_PREP, st);
   hipLaunchKernelGGL(k_gram_mean, dim3(static_cast<unsigned>(nslots)), dim3(256), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1058,6 +1059,7 @@ hipError_t launch_gram_items(const KnnArgs &a, int g, const TableItem *items, in
                                        static_cast<int>(shm));
     if (e != hipSuccess) return e;
   }
+  TimedLaunch timed(EDM_KF_FILTER_SCAN, st);
   hipLaunchKernelGGL(fns[g], dim3(static_cast<unsigned>(n_items)), dim3(kGramThreads), shm, st, a,
                      items);
   return hipGetLastError();
@@ -1078,6 +1080,7 @@ hipError_t launch_gram_group(const KnnArgs &a, int lo, int hi, int nslots, int64
     if (e != hipSuccess) return e;
   }
   const unsigned gx = static_cast<unsigned>((L_max + kKnnThreads - 1) / kKnnThreads);
+  TimedLaunch timed(EDM_KF_FILTER_SCAN, st);
   constexpr int kMaxY = 32768;
   for (int s0 = 0; s0 < nslots; s0 += kMaxY) {
     const int ny = nslots - s0 < kMaxY ? nslots - s0 : kMaxY;

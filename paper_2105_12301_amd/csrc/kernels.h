@@ -12,6 +12,18 @@ namespace edm {
 
 struct Mom;
 
+// Records a HIP event pair on `st` around the launches made during its
+// lifetime and attributes them to kernel family `family` (EDM_KF_*), when
+// the calling thread is inside a TimingScope of a context with timing on;
+// otherwise does nothing.
+struct TimedLaunch {
+  TimedLaunch(int family, hipStream_t st);
+  ~TimedLaunch();
+  int family;
+  hipStream_t st;
+  hipEvent_t start = nullptr;
+};
+
 constexpr int kKnnThreads = 256;  // 4 waves of 64 query points per workgroup
 
 // Arguments of the fused embedding + distance + top-k + weights kernel.
@@ -70,7 +82,7 @@ struct TableItem {
 // (bucket_ids[bucket_at[E] + first ...]) against a group of up to
 // kLookupItemLibs libraries (LookupArgs::item_libs[lib ... lib + nlib - 1],
 // longest first), one wave per library.
-constexpr int kLookupItemMaxTargets = 16;  // T of a LookupItem is at most this
+constexpr int kLookupItemMaxTargets = 16;  // T of a LookupItem: 1, 2, 4, 8 or 16
 constexpr int kLookupItemLibs = 16;        // libraries of a LookupItem, at most
 struct LookupItem {
   int32_t lib;    // first entry of the item's libraries in item_libs
@@ -169,6 +181,10 @@ hipError_t launch_lookup_items(const LookupArgs &a, int E, const LookupItem *ite
                                hipStream_t st);
 
 hipError_t launch_lookup(const LookupArgs &a, int nslots, int64_t m_max, hipStream_t st);
+
+// Targets per staged lookup tile for a window of m samples: the largest of
+// 16, 8, 4, 2, 1 whose tile fits the lookup kernels' 160 KB of LDS.
+int lookup_tile_targets(int64_t m);
 
 // Sweep epilogue: merge the per-block moments into rho[N][E_max] and pick
 // E_opt (smallest E with the largest non-NaN rho).

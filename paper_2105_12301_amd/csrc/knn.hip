@@ -289,6 +289,7 @@ hipError_t launch_knn(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t s
   const dim3 grid_x(static_cast<unsigned>((m_max + kKnnThreads - 1) / kKnnThreads));
   const size_t shm = static_cast<size_t>(L_max) * sizeof(float);
   LaunchFn fn = (a.k == a.E + 1 && a.E >= 1 && a.E <= EDM_E_MAX) ? fast[a.E - 1] : generic[a.k - 1];
+  TimedLaunch timed(EDM_KF_EXACT_SCAN, st);
   constexpr int kMaxY = 32768;
   for (int s0 = 0; s0 < nslots; s0 += kMaxY) {
     const int ny = nslots - s0 < kMaxY ? nslots - s0 : kMaxY;

@@ -1,26 +1,38 @@
 // Batched simplex lookup with the Pearson skill computed on the fly
 // (kEDM paper: Section 2.1 steps 3-4, Section 3.4 and Algorithm 3).
 //
-// A (library, target) pair is computed by one wave: its lanes walk the query
-// points p = lane, lane + 64, ..., read the table row of p (K indices and
-// weights), gather the K neighbours' futures of the target from LDS, and
-// accumulate float64 sums of the observation and the prediction, both
-// relative to the target's first staged sample (the weights sum to one, so
-// the prediction minus that sample is the weighted sum of the gathered
-// samples minus it; the float32 error stays proportional to the target's
-// spread).  The sums are reduced over the wave by a fixed butterfly, so a
-// pair's result does not depend on which kernel computed it or on how many
-// targets share the wave: the grid kernel, the work-list kernel of the plan
-// and every form are bit-identical.
+// Data layout.  A workgroup stages a tile of T targets (T in 1, 2, 4, 8, 16,
+// as many as fit 160 KB of LDS for the window) over the window that its
+// libraries' tables can touch, interleaved: vs[e][t] = y_t[off + e] - c_t with
+// c_t = y_t[off], off = (E-1)*tau + Tp.  One neighbour index q then addresses
+// the T targets' samples as one contiguous LDS segment, so a wave reads them
+// with one 128-, 64- or 32-bit access per lane instead of T scattered 32-bit
+// gathers.
 //
-// Grid kernel: a workgroup stages a tile of T targets of one E (the window
-// [t(0)+Tp, t(nq-1)+Tp] the tables can touch) and its 8 waves run 8
-// libraries' tables against them, each wave reusing every table row for the
-// T targets (8 waves: two workgroups of 64 KB staging fill a CU with 16
-// waves).  Work-list kernel: one item (a group of up to 16 libraries of
-// similar length, T <= 16 targets staged in up to 160 KB) per workgroup of 16
-// waves; wave w runs library w against the staged targets, reusing each table
-// row for up to 4 targets.
+// Lane layout.  A wave walks one library's table: lane = 4 g + s, query group
+// g = 0..15 handles the queries p = g, g + 16, g + 32, ... and sub-lane s the
+// targets s*TPL .. s*TPL + TPL - 1 of the tile (TPL = T/4 targets per lane, at
+// least 1; for T < 4 some sub-lanes idle).  Per query the lane reads the table
+// row (K indices and weights, shared by the 4 lanes of the group), gathers
+// vs[q_i][targets] for i = 0..K-1 and accumulates the prediction
+// yhat = sum_i w_i (y(t(q_i)+Tp) - c) with one float32 fused multiply-add per
+// neighbour in index order, and float64 sums of the observation o = vs[p] and
+// yhat: so, sp, soo, spp, sop.  The prediction is taken relative to c (the
+// weights sum to one), which keeps float32 cancellation proportional to the
+// target's spread.
+//
+// Every pair's arithmetic is fixed: per query group the float64 sums run over
+// p in increasing order, then the 16 group sums meet in a butterfly over the
+// lane bits of g (masks 4, 8, 16, 32).  It does not depend on T, on which
+// kernel ran the pair or on how many libraries or targets shared a
+// workgroup, so every kernel here and every form of the library give
+// bit-identical rho.
+//
+// Grid kernel: blockIdx.x = tile of targets, blockIdx.y = group of 16
+// library slots (one wave each); consecutive workgroups share their
+// libraries' tables in L2.  Work-list kernel (batched plan): one item = a
+// group of up to 16 libraries of similar length (longest first) against one
+// tile, workgroups persistent or one per item.
 #include <array>
 #include <utility>
 
@@ -31,81 +43,121 @@
 namespace edm {
 namespace {
 
-constexpr int kTMax = 8;               // targets per grid workgroup, upper bound
-constexpr int kItemTMax = kLookupItemMaxTargets;
-// Work-list kernel: one wave per library of an item, so every CU keeps 16
-// waves busy however few targets of a long series fit its LDS.
-constexpr int kItemThreads = kLookupItemLibs * 64;
-// targets per table pass of a wave (fewer for the widest rows: registers)
-template <int K>
-constexpr int wave_targets() {
-  return K <= 20 ? 4 : 2;
-}
-constexpr int kGridWaves = 8;  // libraries per grid workgroup (one wave each)
-constexpr int kGridThreads = kGridWaves * kWave;
-constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS for staged targets
+constexpr int kGroups = 16;                  // query groups per wave
+constexpr int kSubs = 4;                     // lanes per query group
+constexpr int kWaves = kLookupItemLibs;      // libraries per workgroup, one wave each
+constexpr int kThreads = kWaves * kWave;     // 1024
+constexpr int64_t kLdsFloats = 40 * 1024;    // 160 KB of staged targets
+
+static_assert(kGroups * kSubs == kWave, "lane layout");
+static_assert(kLookupItemMaxTargets == 16, "tile layout assumes at most 16 targets");
 
 struct Sums {
   double so, sp, soo, spp, sop;
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
-  return v;
+template <int N>
+struct VecOf;
+template <>
+struct VecOf<1> {
+  using type = float;
+};
+template <>
+struct VecOf<2> {
+  using type = float2;
+};
+template <>
+struct VecOf<4> {
+  using type = float4;
+};
+
+template <int TPL>
+__device__ __forceinline__ void lds_read(const float *p, float (&v)[TPL]) {
+  using V = typename VecOf<TPL>::type;
+  const V x = *reinterpret_cast<const V *>(p);
+  if constexpr (TPL == 1) {
+    v[0] = x;
+  } else if constexpr (TPL == 2) {
+    v[0] = x.x;
+    v[1] = x.y;
+  } else {
+    v[0] = x.x;
+    v[1] = x.y;
+    v[2] = x.z;
+    v[3] = x.w;
+  }
 }
 
-// Skill sums of one wave for TW targets (ok[t] false: skipped) through the
-// table (tidx, tw) [m][K].  yt[t]: the target's staged window in LDS.
-// pred[t] (or null): prediction output row.
-template <int K, int TW>
-__device__ __forceinline__ void wave_pairs(const int32_t *__restrict__ tidx,
+// Skill sums of one wave's library against the staged tile (row stride T
+// floats).  Lane (g, s) handles targets s*TPL + u of the tile; every lane
+// returns the wave totals of its targets.  pred[u] (or null): prediction row
+// of target u of the lane, written as yhat + c[u].
+template <int K, int TPL, bool kPred>
+__device__ __forceinline__ void tile_pairs(const int32_t *__restrict__ tidx,
                                            const float *__restrict__ tw, const int m,
-                                           const float *const (&yt)[TW], const bool (&ok)[TW],
-                                           float *const (&pred)[TW], Sums (&s)[TW]) {
+                                           const float *vs, const int T, const int lgT,
+                                           float *const (&pred)[TPL], const float (&c)[TPL],
+                                           Sums (&s)[TPL]) {
   const int lane = threadIdx.x & (kWave - 1);
-  float ct[TW];
+  const int g = lane >> 2;
+  const int sub = lane & (kSubs - 1);
+  // idle sub-lanes (T < 4) read sub-lane 0's targets; their sums are unused
+  const int col = sub * TPL < T ? sub * TPL : 0;
+  const float *base = vs + col;
 #pragma unroll
-  for (int t = 0; t < TW; ++t) {
-    s[t] = Sums{0.0, 0.0, 0.0, 0.0, 0.0};
-    ct[t] = ok[t] ? yt[t][0] : 0.0f;
-  }
-  for (int p = lane; p < m; p += kWave) {
-    int qi[K];
-    float wi[K];
+  for (int u = 0; u < TPL; ++u) s[u] = Sums{0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int p = g; p < m; p += kGroups) {
     const int64_t row = static_cast<int64_t>(p) * K;
+    int q[K];
+    float w[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      qi[i] = tidx[row + i];
-      wi[i] = tw[row + i];
+      q[i] = tidx[row + i];
+      w[i] = tw[row + i];
     }
+    float yh[TPL];
 #pragma unroll
-    for (int t = 0; t < TW; ++t) {
-      if (ok[t]) {
-        const float *y = yt[t];
-        float yh = 0.0f;
+    for (int u = 0; u < TPL; ++u) yh[u] = 0.0f;
+    // gathers in chunks of kChunk neighbours (bounds the registers in flight)
+    constexpr int kChunk = TPL == 4 ? 4 : (TPL == 2 ? 8 : 16);
 #pragma unroll
-        for (int i = 0; i < K; ++i) yh = fmaf(wi[i], y[qi[i]] - ct[t], yh);
-        const double o = static_cast<double>(y[p]) - static_cast<double>(ct[t]);
-        const double ph = static_cast<double>(yh);
-        // explicit fused forms: the same operations in every instantiation
-        s[t].so += o;
-        s[t].sp += ph;
-        s[t].soo = fma(o, o, s[t].soo);
-        s[t].spp = fma(ph, ph, s[t].spp);
-        s[t].sop = fma(o, ph, s[t].sop);
-        if (pred[t]) pred[t][p] = yh + ct[t];
+    for (int i0 = 0; i0 < K; i0 += kChunk) {
+      float v[kChunk][TPL];
+#pragma unroll
+      for (int i = i0; i < (i0 + kChunk < K ? i0 + kChunk : K); ++i)
+        lds_read<TPL>(base + (q[i] << lgT), v[i - i0]);
+#pragma unroll
+      for (int i = i0; i < (i0 + kChunk < K ? i0 + kChunk : K); ++i)
+#pragma unroll
+        for (int u = 0; u < TPL; ++u) yh[u] = fmaf(w[i], v[i - i0][u], yh[u]);
+      if (K > kChunk) __builtin_amdgcn_sched_barrier(0);
+    }
+    float ov[TPL];
+    lds_read<TPL>(base + (p << lgT), ov);
+#pragma unroll
+    for (int u = 0; u < TPL; ++u) {
+      const double o = static_cast<double>(ov[u]);
+      const double ph = static_cast<double>(yh[u]);
+      // explicit fused forms: the same operations in every instantiation
+      s[u].so += o;
+      s[u].sp += ph;
+      s[u].soo = fma(o, o, s[u].soo);
+      s[u].spp = fma(ph, ph, s[u].spp);
+      s[u].sop = fma(o, ph, s[u].sop);
+      if constexpr (kPred) {
+        if (pred[u]) pred[u][p] = yh[u] + c[u];
       }
     }
   }
 #pragma unroll
-  for (int t = 0; t < TW; ++t) {
-    if (ok[t]) {  // uniform across the wave
-      s[t].so = wave_sum(s[t].so);
-      s[t].sp = wave_sum(s[t].sp);
-      s[t].soo = wave_sum(s[t].soo);
-      s[t].spp = wave_sum(s[t].spp);
-      s[t].sop = wave_sum(s[t].sop);
+  for (int u = 0; u < TPL; ++u) {
+#pragma unroll
+    for (int msk = kSubs; msk < kWave; msk <<= 1) {
+      s[u].so += __shfl_xor(s[u].so, msk);
+      s[u].sp += __shfl_xor(s[u].sp, msk);
+      s[u].soo += __shfl_xor(s[u].soo, msk);
+      s[u].spp += __shfl_xor(s[u].spp, msk);
+      s[u].sop += __shfl_xor(s[u].sop, msk);
     }
   }
 }
@@ -115,42 +167,96 @@ __device__ __forceinline__ float pair_rho(int m, const Sums &s) {
       mom_rho(mom_from_shifted_sums(static_cast<double>(m), 0.0, 0.0, s.so, s.sp, s.soo, s.spp, s.sop)));
 }
 
-// Stage the window [off, off + n) of T targets into ys[t * ms + e], zero past
-// a target's own length.
-__device__ __forceinline__ void stage_targets(const LookupArgs &a, const int *tgt, int T, int off,
-                                              int n, int ms, float *ys) {
-  bool bad = false;
-  for (int t = 0; t < T; ++t) {
-    const int64_t Ly = a.Ly_dev ? a.Ly_dev[tgt[t]] : a.ldy;
-    const int n_t = static_cast<int>(Ly - off < n ? Ly - off : n);
-    const float *__restrict__ y = a.Y + static_cast<int64_t>(tgt[t]) * a.ldy + off;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-      float v = 0.0f;
-      if (e < n_t) {
-        v = y[e];
-        bad |= !isfinite(v);
-      }
-      ys[t * ms + e] = v;
+// Stage targets tgt[0..Tn) over the window [off, off + n) into vs[e][t]
+// (row stride T, targets Tn..T-1 zero), relative to cs[t] = y_t[off]; zero
+// past a target's own length.  Ends with a barrier.
+__device__ __forceinline__ void stage_tile(const LookupArgs &a, const int *tgt, int Tn, int T,
+                                           int lgT, int off, int n, float *vs, float *cs) {
+  if (static_cast<int>(threadIdx.x) < T) {
+    const int t = threadIdx.x;
+    float c = 0.0f;
+    if (t < Tn) {
+      const int64_t Ly = a.Ly_dev ? a.Ly_dev[tgt[t]] : a.ldy;
+      if (Ly > off) c = a.Y[static_cast<int64_t>(tgt[t]) * a.ldy + off];
     }
+    cs[t] = c;
+  }
+  __syncthreads();
+  bool bad = false;
+  const int total = n * T;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int e = idx >> lgT;
+    const int t = idx & (T - 1);
+    float v = 0.0f;
+    if (t < Tn) {
+      const int64_t Ly = a.Ly_dev ? a.Ly_dev[tgt[t]] : a.ldy;
+      if (off + e < Ly) {
+        const float y = a.Y[static_cast<int64_t>(tgt[t]) * a.ldy + off + e];
+        bad |= !isfinite(y);
+        v = y - cs[t];
+      }
+    }
+    vs[idx] = v;
   }
   if (bad) atomicOr(a.status, 1);
+  __syncthreads();
 }
 
-// Grid kernel: blockIdx.x = tile of T targets, blockIdx.y = group of
-// kGridWaves library slots; ms = LDS row stride (>= every staged window).
-template <int K>
-__global__ __launch_bounds__(kGridThreads) void k_lookup(LookupArgs a, int T, int ms,
-                                                           int nslots, int slot0) {
-  extern __shared__ float ys[];  // [T][ms]
-  const int t0 = static_cast<int>(blockIdx.x) * T;
-  const int sbase = slot0 + static_cast<int>(blockIdx.y) * kGridWaves;
-  const int off = (a.E - 1) * a.tau + a.Tp;
-  int tgt[kTMax];
-  const int Tn = a.ntgt - t0 < T ? a.ntgt - t0 : T;
+// One wave's library (m queries, table tidx/tw) against the staged tile
+// tgt[0..Tn): sums, then rho (and predictions) for the pairs that are
+// defined (target at least as long as the library).
+template <int K, int TPL>
+__device__ __forceinline__ void wave_library(const LookupArgs &a, const int32_t *tidx,
+                                             const float *tw, int lib, int64_t Lx, int m,
+                                             const float *vs, const float *cs, const int *tgt,
+                                             int Tn, int T, int lgT) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int sub = lane & (kSubs - 1);
+  bool ok[TPL];
+  int id[TPL];
+  float c[TPL];
+  float *pred[TPL];
 #pragma unroll
-  for (int t = 0; t < kTMax; ++t) tgt[t] = t < Tn ? (a.tgt_ids ? a.tgt_ids[t0 + t] : t0 + t) : 0;
+  for (int u = 0; u < TPL; ++u) {
+    const int t = sub * TPL + u;
+    const bool in = sub * TPL < T && t < Tn;
+    id[u] = in ? tgt[t] : 0;
+    ok[u] = in && !(a.Ly_dev && a.Ly_dev[id[u]] < Lx);
+    c[u] = in ? cs[t] : 0.0f;
+    pred[u] = (TPL == 1 && ok[u] && a.pred) ? a.pred + static_cast<int64_t>(id[u]) * a.ldpred : nullptr;
+  }
+  Sums s[TPL];
+  // predictions are written only with one target per lane (tiles of at most
+  // 4 targets), which keeps the wider instantiations free of their registers
+  if (TPL == 1 && a.pred)
+    tile_pairs<K, TPL, TPL == 1>(tidx, tw, m, vs, T, lgT, pred, c, s);
+  else
+    tile_pairs<K, TPL, false>(tidx, tw, m, vs, T, lgT, pred, c, s);
+  if (a.rho && lane < kSubs) {
+#pragma unroll
+    for (int u = 0; u < TPL; ++u)
+      if (ok[u]) a.rho[static_cast<int64_t>(lib) * a.ldrho + id[u]] = pair_rho(m, s[u]);
+  }
+}
+
+// Grid kernel: blockIdx.x = tile of T targets (bucket positions
+// [x*T, x*T + T)), blockIdx.y = group of kWaves library slots from slot0;
+// ms bounds every staged window (the dynamic LDS holds T * ms floats).
+template <int K, int TPL>
+__global__ __launch_bounds__(kThreads) void k_lookup(LookupArgs a, int T, int nslots, int slot0) {
+  extern __shared__ float4 lds4[];
+  float *vs = reinterpret_cast<float *>(lds4);
+  __shared__ float cs[kLookupItemMaxTargets];
+  __shared__ int tgt[kLookupItemMaxTargets];
+  const int t0 = static_cast<int>(blockIdx.x) * T;
+  const int sbase = slot0 + static_cast<int>(blockIdx.y) * kWaves;
+  const int off = (a.E - 1) * a.tau + a.Tp;
+  const int Tn = a.ntgt - t0 < T ? a.ntgt - t0 : T;
+  const int lgT = 31 - __builtin_clz(T);
+  if (static_cast<int>(threadIdx.x) < Tn)
+    tgt[threadIdx.x] = a.tgt_ids ? a.tgt_ids[t0 + threadIdx.x] : t0 + static_cast<int>(threadIdx.x);
   int n_blk = 0;  // widest query range of the workgroup's libraries
-  for (int w = 0; w < kGridWaves; ++w) {
+  for (int w = 0; w < kWaves; ++w) {
     const int slot = sbase + w;
     if (slot >= slot0 + nslots) break;
     const int lib = a.lib_ids ? a.lib_ids[slot] : slot;
@@ -159,8 +265,7 @@ __global__ __launch_bounds__(kGridThreads) void k_lookup(LookupArgs a, int T, in
     n_blk = mw > n_blk ? mw : n_blk;
   }
   if (n_blk - 1 < K) return;  // no table in this workgroup (uniform)
-  stage_targets(a, tgt, Tn, off, n_blk, ms, ys);
-  __syncthreads();
+  stage_tile(a, tgt, Tn, T, lgT, off, n_blk, vs, cs);
 
   const int wave = static_cast<int>(threadIdx.x) / kWave;
   const int slot = __builtin_amdgcn_readfirstlane(sbase + wave);
@@ -170,37 +275,22 @@ __global__ __launch_bounds__(kGridThreads) void k_lookup(LookupArgs a, int T, in
   const int m = static_cast<int>(Lx) - off;
   if (m - 1 < K) return;  // the table does not exist for this library
   const int64_t tbl = static_cast<int64_t>(slot) * a.tbl_stride;
-  const float *yt[kTMax];
-  bool ok[kTMax];
-  float *pred[kTMax];
-#pragma unroll
-  for (int t = 0; t < kTMax; ++t) {
-    yt[t] = ys + t * ms;
-    ok[t] = t < Tn && !(a.Ly_dev && a.Ly_dev[tgt[t]] < Lx);  // pair defined
-    pred[t] = (ok[t] && a.pred) ? a.pred + static_cast<int64_t>(tgt[t]) * a.ldpred : nullptr;
-  }
-  Sums s[kTMax];
-  wave_pairs<K, kTMax>(a.idx + tbl, a.w + tbl, m, yt, ok, pred, s);
-  if (a.rho && (threadIdx.x & (kWave - 1)) == 0) {
-#pragma unroll
-    for (int t = 0; t < kTMax; ++t)
-      if (ok[t]) a.rho[static_cast<int64_t>(lib) * a.ldrho + tgt[t]] = pair_rho(m, s[t]);
-  }
+  wave_library<K, TPL>(a, a.idx + tbl, a.w + tbl, lib, Lx, m, vs, cs, tgt, Tn, T, lgT);
 }
 
 // Work-list kernel for one E (K = E + 1): persistent (counter != nullptr:
 // workgroups pull items) or one workgroup per item.  An item stages a tile of
 // targets once, over the window of its longest library, and wave w runs the
-// item's library w against every staged target, kWaveT targets per table
-// pass.  Item fields are made wave-uniform.
+// item's library w against the tile.  Item fields are wave-uniform.
 template <int K>
-__global__ __launch_bounds__(kItemThreads) void k_lookup_items(LookupArgs a,
-                                                                const LookupItem *__restrict__ items,
-                                                                int n_items, int *counter) {
-  extern __shared__ float ys[];
+__global__ __launch_bounds__(kThreads) void k_lookup_items(LookupArgs a,
+                                                            const LookupItem *__restrict__ items,
+                                                            int n_items, int *counter) {
+  extern __shared__ float4 lds4[];
+  float *vs = reinterpret_cast<float *>(lds4);
+  __shared__ float cs[kLookupItemMaxTargets];
+  __shared__ int tgt[kLookupItemMaxTargets];
   __shared__ int item_s;
-  __shared__ int tgt[kItemTMax];
-  constexpr int kWaveT = wave_targets<K>();
   const int E = K - 1;
   const int off = (E - 1) * a.tau + a.Tp;
   const int wave = static_cast<int>(threadIdx.x) / kWave;
@@ -210,7 +300,7 @@ __global__ __launch_bounds__(kItemThreads) void k_lookup_items(LookupArgs a,
       if (trip > 0) break;
       it = static_cast<int>(blockIdx.x);
     } else {
-      __syncthreads();  // the previous item is done with ys, tgt and item_s
+      __syncthreads();  // the previous item is done with vs, cs, tgt and item_s
       if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
       __syncthreads();
       it = __builtin_amdgcn_readfirstlane(item_s);
@@ -222,82 +312,77 @@ __global__ __launch_bounds__(kItemThreads) void k_lookup_items(LookupArgs a,
     const int first = __builtin_amdgcn_readfirstlane(items[it].first);
     const int count = __builtin_amdgcn_readfirstlane(items[it].count);
     const int Tn = count < T ? count : T;
+    const int lgT = 31 - __builtin_clz(T);
     // the first library of an item is its longest: its window covers all
     const int lib0 = __builtin_amdgcn_readfirstlane(a.item_libs[at]);
     const int ms = static_cast<int>((a.Lx_dev ? a.Lx_dev[lib0] : a.Lx_uni) - off);
     if (static_cast<int>(threadIdx.x) < Tn) tgt[threadIdx.x] = a.bucket_ids[a.bucket_at[E] + first + threadIdx.x];
     __syncthreads();
-    if (ms >= 1) stage_targets(a, tgt, Tn, off, ms, ms, ys);
-    __syncthreads();
+    if (ms < 1) continue;  // uniform: nothing of this item can be defined
+    stage_tile(a, tgt, Tn, T, lgT, off, ms, vs, cs);
     if (wave < nlib) {  // uniform per wave
       const int lib = __builtin_amdgcn_readfirstlane(a.item_libs[at + wave]);
       const int64_t Lx = a.Lx_dev ? a.Lx_dev[lib] : a.Lx_uni;
       const int m = static_cast<int>(Lx) - off;
       if (m - 1 >= K) {
         const int64_t o = a.tbl_off[static_cast<int64_t>(lib) * (EDM_E_MAX + 1) + E];
-        for (int t0 = 0; t0 < Tn; t0 += kWaveT) {
-          const float *yt[kWaveT];
-          bool ok[kWaveT];
-          float *pred[kWaveT];
-          int id[kWaveT];
-#pragma unroll
-          for (int u = 0; u < kWaveT; ++u) {
-            const int t = t0 + u;
-            id[u] = tgt[t < Tn ? t : 0];
-            yt[u] = ys + (t < Tn ? t : 0) * ms;
-            ok[u] = t < Tn && !(a.Ly_dev && a.Ly_dev[id[u]] < Lx);
-            pred[u] = nullptr;
-          }
-          Sums s[kWaveT];
-          wave_pairs<K, kWaveT>(a.tbl_idx + o, a.tbl_w + o, m, yt, ok, pred, s);
-          if (a.rho && (threadIdx.x & (kWave - 1)) == 0) {
-#pragma unroll
-            for (int u = 0; u < kWaveT; ++u)
-              if (ok[u]) a.rho[static_cast<int64_t>(lib) * a.ldrho + id[u]] = pair_rho(m, s[u]);
-          }
-        }
+        if (T >= 16)
+          wave_library<K, 4>(a, a.tbl_idx + o, a.tbl_w + o, lib, Lx, m, vs, cs, tgt, Tn, T, lgT);
+        else if (T == 8)
+          wave_library<K, 2>(a, a.tbl_idx + o, a.tbl_w + o, lib, Lx, m, vs, cs, tgt, Tn, T, lgT);
+        else
+          wave_library<K, 1>(a, a.tbl_idx + o, a.tbl_w + o, lib, Lx, m, vs, cs, tgt, Tn, T, lgT);
       }
     }
   }
 }
 
-using LaunchFn = hipError_t (*)(const LookupArgs &, dim3, size_t, int, int, int, int, hipStream_t);
+using LaunchFn = hipError_t (*)(const LookupArgs &, dim3, size_t, int, int, int, hipStream_t);
 
-template <int K>
-hipError_t launch_k(const LookupArgs &a, dim3 grid, size_t shm, int T, int ms, int nslots,
-                    int slot0, hipStream_t st) {
-  const void *fn = reinterpret_cast<const void *>(&k_lookup<K>);
+template <int K, int TPL>
+hipError_t launch_k(const LookupArgs &a, dim3 grid, size_t shm, int T, int nslots, int slot0,
+                    hipStream_t st) {
+  const void *fn = reinterpret_cast<const void *>(&k_lookup<K, TPL>);
   if (shm > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(shm));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_lookup<K>), grid, dim3(kGridThreads), shm, st, a, T, ms, nslots, slot0);
+  hipLaunchKernelGGL((k_lookup<K, TPL>), grid, dim3(kThreads), shm, st, a, T, nslots, slot0);
   return hipGetLastError();
 }
 
-template <size_t... I>
+template <int TPL, size_t... I>
 constexpr auto make_table(std::index_sequence<I...>) {
-  return std::array<LaunchFn, sizeof...(I)>{&launch_k<static_cast<int>(I) + 1>...};
+  return std::array<LaunchFn, sizeof...(I)>{&launch_k<static_cast<int>(I) + 1, TPL>...};
 }
 
 }  // namespace
 
+int lookup_tile_targets(int64_t m) {
+  int T = kLookupItemMaxTargets;
+  while (T > 1 && static_cast<int64_t>(T) * m > kLdsFloats) T >>= 1;
+  return T;
+}
+
 hipError_t launch_lookup(const LookupArgs &a, int nslots, int64_t m_max, hipStream_t st) {
-  static const auto table = make_table(std::make_index_sequence<EDM_K_MAX>{});
+  static const auto t4 = make_table<4>(std::make_index_sequence<EDM_K_MAX>{});
+  static const auto t2 = make_table<2>(std::make_index_sequence<EDM_K_MAX>{});
+  static const auto t1 = make_table<1>(std::make_index_sequence<EDM_K_MAX>{});
   if (nslots <= 0 || a.ntgt <= 0 || m_max <= 0) return hipSuccess;
-  int T = static_cast<int>(kLdsBudget / (m_max * static_cast<int64_t>(sizeof(float))));
-  if (T < 1) T = 1;
-  if (T > kTMax) T = kTMax;
-  if (T > a.ntgt) T = a.ntgt;
-  const int ms = static_cast<int>(m_max);
+  if (a.k < 1 || a.k > EDM_K_MAX || m_max > kLdsFloats) return hipErrorInvalidValue;
+  int T = lookup_tile_targets(m_max);
+  if (a.pred && T > 4) T = 4;                 // the prediction-writing form
+  while (T > 1 && T / 2 >= a.ntgt) T >>= 1;  // no wider than the target count needs
   const size_t shm = static_cast<size_t>(T) * static_cast<size_t>(m_max) * sizeof(float);
   const unsigned gx = static_cast<unsigned>((a.ntgt + T - 1) / T);
-  constexpr int kMaxY = 32768 * kGridWaves;
+  const auto &table = T >= 16 ? t4 : (T == 8 ? t2 : t1);
+  TimedLaunch timed(EDM_KF_LOOKUP, st);
+  constexpr int kMaxY = 32768 * kWaves;
   for (int s0 = 0; s0 < nslots; s0 += kMaxY) {
     const int ns = nslots - s0 < kMaxY ? nslots - s0 : kMaxY;
-    const unsigned gy = static_cast<unsigned>((ns + kGridWaves - 1) / kGridWaves);
-    hipError_t e = table[a.k - 1](a, dim3(gx, gy), shm, T, ms, ns, s0, st);
+    const unsigned gy = static_cast<unsigned>((ns + kWaves - 1) / kWaves);
+    hipError_t e = table[a.k - 1](a, dim3(gx, gy), shm, T, ns, s0, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -314,7 +399,7 @@ hipError_t launch_lookup_items(const LookupArgs &a, int E, const LookupItem *ite
                                     EDM_FN(11), EDM_FN(12), EDM_FN(13), EDM_FN(14), EDM_FN(15),
                                     EDM_FN(16), EDM_FN(17), EDM_FN(18), EDM_FN(19), EDM_FN(20)};
 #undef EDM_FN
-  if (E < 1 || E > EDM_E_MAX) return hipErrorInvalidValue;
+  if (E < 1 || E > EDM_E_MAX || lds_floats > kLdsFloats) return hipErrorInvalidValue;
   const size_t shm = static_cast<size_t>(lds_floats) * sizeof(float);
   const void *fn = reinterpret_cast<const void *>(fns[E - 1]);
   if (shm > 65536) {
@@ -322,13 +407,14 @@ hipError_t launch_lookup_items(const LookupArgs &a, int E, const LookupItem *ite
                                        static_cast<int>(shm));
     if (e != hipSuccess) return e;
   }
+  TimedLaunch timed(EDM_KF_LOOKUP, st);
   if (wg_per_cu <= 0) {
-    hipLaunchKernelGGL(fns[E - 1], dim3(static_cast<unsigned>(n_items)), dim3(kItemThreads), shm,
+    hipLaunchKernelGGL(fns[E - 1], dim3(static_cast<unsigned>(n_items)), dim3(kThreads), shm,
                        st, a, items, n_items, static_cast<int *>(nullptr));
   } else {
     int grid = wg_per_cu * n_cu;
     if (grid > n_items) grid = n_items;
-    hipLaunchKernelGGL(fns[E - 1], dim3(static_cast<unsigned>(grid)), dim3(kItemThreads), shm, st,
+    hipLaunchKernelGGL(fns[E - 1], dim3(static_cast<unsigned>(grid)), dim3(kThreads), shm, st,
                        a, items, n_items, counter);
   }
   return hipGetLastError();

@@ -102,6 +102,7 @@ hipError_t launch_sweep_finalize(const Mom *mom, int32_t mom_blocks, const int64
                                  const uint32_t *cand, float *rho, int32_t *E_opt,
                                  hipStream_t st) {
   if (N <= 0) return hipSuccess;
+  TimedLaunch timed(EDM_KF_FINALIZE, st);
   hipLaunchKernelGGL(k_sweep_finalize, dim3(grid_for(N, 64)), dim3(64), 0, st, mom, mom_blocks,
                      L_dev, N, E_max, tau, Tp, cand, rho, E_opt);
   return hipGetLastError();
@@ -110,6 +111,7 @@ hipError_t launch_sweep_finalize(const Mom *mom, int32_t mom_blocks, const int64
 hipError_t launch_candidates(const float *logits, int64_t N, int32_t E_max, int32_t m_top,
                              float min_conf, uint32_t *cand, hipStream_t st) {
   if (N <= 0) return hipSuccess;
+  TimedLaunch timed(EDM_KF_OTHER, st);
   hipLaunchKernelGGL(k_candidates, dim3(grid_for(N, 64)), dim3(64), 0, st, logits, N, E_max,
                      m_top, min_conf, cand);
   return hipGetLastError();
@@ -117,6 +119,7 @@ hipError_t launch_candidates(const float *logits, int64_t N, int32_t E_max, int3
 
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  TimedLaunch timed(EDM_KF_OTHER, st);
   hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
@@ -124,6 +127,7 @@ hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st) {
 hipError_t launch_embed(const float *x, int64_t L, int32_t E, int32_t tau, float *out,
                         int *status, hipStream_t st) {
   const int64_t n = L - static_cast<int64_t>(E - 1) * tau;
+  TimedLaunch timed(EDM_KF_OTHER, st);
   hipLaunchKernelGGL(k_embed, dim3(grid_for(n * E, 256)), dim3(256), 0, st, x, n, E, tau, out,
                      status);
   return hipGetLastError();

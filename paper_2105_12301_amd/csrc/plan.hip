@@ -100,7 +100,7 @@ void edm_tune_default(edm_tune *t) {
   if (!t) return;
   t->tables_wg_per_cu = 0;
   t->lookup_wg_per_cu = 0;
-  t->lookup_targets = 4;
+  t->lookup_targets = 16;
 }
 
 void edm_ccm_plan_destroy(edm_ctx *ctx, edm_plan *plan) {
@@ -251,8 +251,10 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
         if (grp.empty()) return;
         const int64_t m = Lx[grp.front()] - (E - 1) - Tp;  // the longest window
         const int64_t cnt = defined(E, Lx[grp.back()]);
-        int64_t T = 40000 / m;  // staged targets of an item: at most 160 KB of LDS
-        T = std::max<int64_t>(1, std::min<int64_t>(T, tn.lookup_targets));
+        // staged targets of an item: a power of two up to the tune's count
+        // whose tile fits the lookup kernel's LDS
+        int64_t T = edm::lookup_tile_targets(m);
+        while (T > tn.lookup_targets) T >>= 1;
         B.lds_floats[E] = std::max(B.lds_floats[E], T * m);
         const int32_t at = static_cast<int32_t>(item_libs.size());
         item_libs.insert(item_libs.end(), grp.begin(), grp.end());
@@ -439,6 +441,8 @@ extern "C" int edm_ccm_plan_run(edm_ctx *ctx, edm_plan *P, const float *X, const
     P->grho = rho;
     P->gstream = ctx->stream;
   }
+  TimingScope timing_scope(ctx);
+  edm::TimedLaunch timed(EDM_KF_PLAN, ctx->stream);
   EDM_HIP(ctx, hipGraphLaunch(P->exec, ctx->stream));
   return EDM_OK;
 }

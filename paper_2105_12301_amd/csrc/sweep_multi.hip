@@ -265,6 +265,7 @@ hipError_t launch_sweep_multi(const KnnArgs &a, int nslots, int64_t L_max, hipSt
     if (lo > hi) break;
     const std::array<LaunchFn, 8> &t = lo == 1 ? t1 : lo == 9 ? t9 : lo == 13 ? t13 : lo == 16 ? t16 : t19;
     LaunchFn fn = t[hi - lo];
+    TimedLaunch timed(EDM_KF_BATCHED_SCAN, st);
     constexpr int kMaxY = 32768;
     for (int s0 = 0; s0 < nslots; s0 += kMaxY) {
       const int ny = nslots - s0 < kMaxY ? nslots - s0 : kMaxY;
@@ -296,6 +297,7 @@ hipError_t launch_tables_persistent(const KnnArgs &a, int group, const TableItem
   if (group < 0 || group > 5) return hipErrorInvalidValue;
   const size_t shm = static_cast<size_t>(L_max) * sizeof(float);
   const void *fn = reinterpret_cast<const void *>(fns[group]);
+  TimedLaunch timed(EDM_KF_BATCHED_SCAN, st);
   if (shm > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(shm));

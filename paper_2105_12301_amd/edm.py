@@ -46,7 +46,12 @@ EXPORTS = (
     "edm_net_adam",
     "edm_select_E",
     "edm_tune_default", "edm_ccm_plan_create", "edm_ccm_plan_run", "edm_ccm_plan_destroy",
+    "edm_ctx_set_timing", "edm_ctx_timing",
 )
+
+# kernel families of edm_ctx_timing (include/edm.h, EDM_KF_*)
+KERNEL_FAMILIES = ("exact_scan", "batched_scan", "filter_prep", "filter_scan", "tables_from_sweep",
+                   "lookup", "finalize", "other", "distances", "row_topk", "group", "plan")
 
 
 class Tune(ctypes.Structure):
@@ -108,6 +113,8 @@ def load_library(path: str = LIB_PATH):
         lib.edm_ccm_plan_create.argtypes = [_p, _p, _i64, _i64, _p, _i64, _i64, _p, _i32,
                                             ctypes.POINTER(Tune), ctypes.POINTER(_p)]
         lib.edm_ccm_plan_run.argtypes = [_p, _p, _p, _p, _p]
+        lib.edm_ctx_set_timing.argtypes = [_p, ctypes.c_int]
+        lib.edm_ctx_timing.argtypes = [_p, _p, _p]
         lib.edm_ccm_plan_destroy.argtypes = [_p, _p]
         lib.edm_ccm_plan_destroy.restype = None
         for name in EXPORTS:
@@ -170,6 +177,18 @@ class Context:
 
     def sync(self):
         _check(load_library().edm_sync(self._h), self._h)
+
+    def set_timing(self, on: bool = True):
+        """Time every kernel launch by family (edm_ctx_set_timing); clears totals."""
+        _check(load_library().edm_ctx_set_timing(self._h, int(bool(on))), self._h)
+
+    def timing(self):
+        """{family: (ms, launches)} recorded since the last call (edm_ctx_timing)."""
+        n = len(KERNEL_FAMILIES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(load_library().edm_ctx_timing(self._h, ctypes.cast(ms, _p), ctypes.cast(cnt, _p)), self._h)
+        return {f: (float(ms[i]), int(cnt[i])) for i, f in enumerate(KERNEL_FAMILIES)}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -130,3 +130,17 @@ def test_net_validation(lib):
     assert s(NULL, P, L, 2, 100, 20, 1, 1, P, 0, 0.0, P, P, ctypes.byref(nfb)) == edm.EDM_E_ARG
     assert s(NULL, P, L, 2, 100, 20, 1, 1, P, 2, 1.5, P, P, ctypes.byref(nfb)) == edm.EDM_E_ARG
     assert s(NULL, P, L, 2, 100, 20, 1, 1, NULL, 2, 0.5, P, P, ctypes.byref(nfb)) == edm.EDM_E_ARG
+
+
+def test_kernel_family_names_follow_the_header():
+    src = open(os.path.join(ROOT, "include", "edm.h")).read()
+    fams = dict((int(v), k) for k, v in re.findall(r"\bEDM_KF_([A-Z_]+)\s*=\s*(\d+)", src))
+    count = fams.pop(max(fams))
+    assert count == "COUNT" and len(fams) == len(edm.KERNEL_FAMILIES)
+    for i, name in enumerate(edm.KERNEL_FAMILIES):
+        assert fams[i].lower() == name, (i, fams[i], name)
+
+
+def test_timing_calls_reject_null_context(lib):
+    assert lib.edm_ctx_set_timing(NULL, 1) == edm.EDM_E_ARG
+    assert lib.edm_ctx_timing(NULL, NULL, NULL) == edm.EDM_E_ARG
