@@ -49,6 +49,12 @@ notes):
   0 when no E is feasible.
 * Uneven lengths: pair (library i, target j) is defined iff L_j >= L_i, and the
   target is read on the library's time axis [0, L_i).  Undefined pairs are NaN.
+* Library subsampling (the convergence test of CCM, which Section 2.1 builds
+  on but the paper does not run): a library of size l is a set of l distinct
+  embedded points drawn at random by the caller; every query point p of the
+  whole series is predicted from its k nearest neighbours inside that set
+  (p itself and its exclusion window barred), and rho is taken over all query
+  points.  The random sets are inputs, not drawn here.
 """
 from __future__ import annotations
 
@@ -67,6 +73,8 @@ __all__ = [
     "simplex_sweep",
     "select_E",
     "ccm",
+    "knn_subset",
+    "ccm_subsample",
 ]
 
 
@@ -269,3 +277,44 @@ def ccm(X, Lx, Y, Ly, E_tgt, tau: int = 1, Tp: int = 0, lib_rows=None,
             yhat, obs = lookup(idx, wbar, Y[j, :L], E, tau, Tp)
             rho[a, b] = pearson(obs, yhat)
     return rho
+
+
+def knn_subset(x, E: int, tau: int, Tp: int, cand, k: int = 0, excl: int = 0):
+    """Neighbour table of every query p in [0, n - Tp) with the candidates
+    restricted to the set ``cand`` (distinct indices in [0, n - Tp)): the k
+    smallest (key, q) over q in cand with |q - p| > excl, ascending (Section
+    2.1 step 2 on a library subsample).  Returns (idx int32 [nq][k], key
+    float32 [nq][k])."""
+    if k == 0:
+        k = E + 1
+    n = n_embedded(len(x), E, tau)
+    m = n - Tp
+    cand = np.unique(np.asarray(cand, dtype=np.int64))
+    if cand.size and (cand[0] < 0 or cand[-1] >= m):
+        raise ValueError("candidate index outside [0, n - Tp)")
+    if cand.size - (2 * excl + 1) < k:
+        raise ValueError("library subset too small for k neighbours")
+    K = knn_keys(x, E, tau, Tp)
+    idx = np.empty((m, k), dtype=np.int32)
+    key = np.empty((m, k), dtype=np.float32)
+    for p in range(m):
+        c = cand[np.abs(cand - p) > excl]
+        ck = K[p, c]
+        order = np.argsort(ck, kind="stable")[:k]   # cand ascending: ties keep lower q first
+        idx[p] = c[order]
+        key[p] = ck[order]
+    return idx, key
+
+
+def ccm_subsample(x, y, E: int, tau: int, Tp: int, subsets, k: int = 0, excl: int = 0):
+    """Cross-map skill of target y from library x for each library subsample
+    (one row of ``subsets`` each): table from knn_subset, then the weights,
+    lookup and Pearson of Section 2.1 steps 3-4 over every query point.
+    Returns rho float64 [len(subsets)]."""
+    out = np.empty(len(subsets))
+    for s, cand in enumerate(subsets):
+        idx, _ = knn_subset(x, E, tau, Tp, cand, k, excl)
+        _, wbar = weights(x, idx, E, tau)
+        yhat, obs = lookup(idx, wbar, y, E, tau, Tp)
+        out[s] = pearson(obs, yhat)
+    return out

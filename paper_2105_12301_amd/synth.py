@@ -41,6 +41,7 @@ __all__ = [
     "ramp",
     "tiled_period",
     "net_init_params",
+    "library_subsets",
 ]
 
 
@@ -238,6 +239,21 @@ def net_init_params(C: int, seed: int = 0, kw: int = 7, n_class: int = 20) -> np
             lim = np.sqrt(6.0 / int(np.prod(shp[1:])))
             parts.append(rng.uniform(-lim, lim, size=shp))
     return np.concatenate([q.ravel() for q in parts]).astype(np.float32)
+
+
+def library_subsets(seed: int, m: int, sizes, n_samples: int) -> list:
+    """Random library subsamples for a convergence run: for every size l in
+    ``sizes``, ``n_samples`` sets of l distinct indices drawn uniformly from
+    [0, m) without replacement, each sorted ascending.  Returns a list over
+    sizes of int32 arrays [n_samples][l]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for l in sizes:
+        a = np.empty((n_samples, int(l)), dtype=np.int32)
+        for s in range(n_samples):
+            a[s] = np.sort(rng.choice(m, size=int(l), replace=False))
+        out.append(a)
+    return out
 
 
 # --- closed-form fixtures used by the pins -------------------------------

@@ -420,3 +420,78 @@ def test_exclusion_radius_feasibility():
     with pytest.raises(ValueError):
         O.knn(x[0], 8, 1, 1, excl=2)
     O.knn(x[0], 7, 1, 1, excl=2)
+
+
+# --- library subsampling (CCM convergence) ---------------------------------
+
+def brute_knn_subset(x, E, tau, Tp, k, cand, excl=0):
+    n = len(x) - (E - 1) * tau
+    m = n - Tp
+    out = []
+    for p in range(m):
+        c = sorted((brute_key(x, p, q, E, tau), q) for q in cand if abs(q - p) > excl)
+        out.append([q for _, q in c[:k]])
+    return np.array(out)
+
+
+@pytest.mark.parametrize("E,tau,Tp,excl", [(1, 1, 0, 0), (2, 1, 1, 0), (3, 2, 0, 1), (4, 1, 1, 2)])
+def test_subset_matches_bruteforce(E, tau, Tp, excl):
+    x = tiny_series(5, 56)
+    m = len(x) - (E - 1) * tau - Tp
+    rng = np.random.default_rng(E + 10 * excl)
+    for size in (E + 2 + 2 * excl, m // 2, m - 3):
+        cand = np.sort(rng.choice(m, size=size, replace=False))
+        idx, _ = O.knn_subset(x, E, tau, Tp, cand, excl=excl)
+        np.testing.assert_array_equal(idx, brute_knn_subset(x, E, tau, Tp, E + 1, cand, excl))
+
+
+@pytest.mark.parametrize("E,tau,Tp,excl", [(1, 1, 1, 0), (3, 1, 0, 0), (2, 2, 1, 3)])
+def test_subset_of_everything_is_the_plain_method(E, tau, Tp, excl):
+    X, _ = synth.coupled_logistic_pairs(seed=1, n_pairs=1, L=300)
+    x, y = X[1], X[0]
+    m = len(x) - (E - 1) * tau - Tp
+    idx_s, key_s = O.knn_subset(x, E, tau, Tp, np.arange(m), excl=excl)
+    idx, key = O.knn(x, E, tau, Tp, excl=excl)
+    np.testing.assert_array_equal(idx_s, idx)
+    np.testing.assert_array_equal(key_s.view(np.uint32), key.view(np.uint32))
+    r = O.ccm_subsample(x, y, E, tau, Tp, [np.arange(m)], excl=excl)
+    assert r[0] == O.simplex_rho(x, y, E, tau, Tp, excl=excl)
+
+
+def test_subset_ramp_closed_form():
+    # X[t] = t, E = 1, library = the even points: an odd interior query's two
+    # nearest are p - 1 and p + 1 (equal keys, lower index first); an even
+    # one (a library member) skips itself: p - 2, p + 2.
+    x = np.arange(60, dtype=np.float32)
+    cand = np.arange(0, 60, 2)
+    idx, _ = O.knn_subset(x, 1, 1, 0, cand)
+    for p in range(4, 55):
+        want = [p - 1, p + 1] if p % 2 else [p - 2, p + 2]
+        assert idx[p].tolist() == want
+
+
+def test_subset_too_small_raises():
+    x = np.arange(40, dtype=np.float32)
+    with pytest.raises(ValueError):
+        O.knn_subset(x, 2, 1, 0, [1, 5, 9])          # 3 - 1 < k = 3
+    with pytest.raises(ValueError):
+        O.knn_subset(x, 1, 1, 0, [0, 45])             # index outside [0, m)
+
+
+def test_convergence_with_library_size():
+    # CCM's convergence criterion: predicting the driver from the response's
+    # shadow manifold improves as the library grows, and at the full library
+    # reaches the plain method's value.
+    X, _ = synth.coupled_logistic_pairs(seed=1, n_pairs=1, L=600)
+    x, y = X[1], X[0]            # library: response; target: its driver
+    E, m = 2, 600 - 1
+    sizes = (12, 50, 200, m)
+    subs = synth.library_subsets(3, m, sizes, 6)
+    means = [float(np.mean(O.ccm_subsample(x, y, E, 1, 0, s))) for s in subs]
+    assert all(a < b for a, b in zip(means, means[1:])), means
+    assert abs(means[-1] - O.simplex_rho(x, y, E, 1, 0)) < 1e-12
+    assert means[0] < means[-1] - 0.05
+    # the other direction (the driver's manifold does not encode the
+    # response) stays far lower at every size
+    rev = [float(np.mean(O.ccm_subsample(y, x, E, 1, 0, s))) for s in subs]
+    assert max(rev) < means[-1] - 0.2, rev
