@@ -71,6 +71,33 @@ class Surrogate:
         return edm.edm_select_E(X, self.logits(X), lengths=lengths, E_max=E_max, Tp=Tp,
                                 m_top=m_top, min_conf=min_conf, ctx=self.ctx)
 
+    def calibrate(self, X, rho_sweep, m_top: int = 3, max_loss: float = 0.01) -> float:
+        """Confidence threshold for the fallback, chosen on held-out series.
+
+        X: held-out series (device), rho_sweep: their full-sweep skill
+        [N][20] (edm_simplex_sweep).  A series whose top softmax probability
+        is at least c keeps the best of its m_top proposed E, losing
+        max(rho) - max(rho at the proposals); below c it takes the full sweep
+        and loses nothing.  Returns the smallest c (a probability) for which no
+        held-out series loses more than max_loss."""
+        lg = self.logits(X).double().cpu().numpy()
+        rs = rho_sweep.double().cpu().numpy()
+        lg = lg - lg.max(axis=1, keepdims=True)
+        p = np.exp(lg)
+        conf = p.max(axis=1) / p.sum(axis=1)
+        top = np.argsort(-lg, axis=1, kind="stable")[:, :m_top]
+        best = np.nanmax(np.where(np.isnan(rs), -np.inf, rs), axis=1)
+        got = np.take_along_axis(np.where(np.isnan(rs), -np.inf, rs), top, axis=1).max(axis=1)
+        loss = best - got
+        order = np.argsort(conf)
+        # suffix maximum of the loss over series at least as confident
+        suf = np.maximum.accumulate(loss[order][::-1])[::-1]
+        ok = np.nonzero(suf <= max_loss)[0]
+        if ok.size == 0:
+            return 1.0
+        c = float(conf[order][ok[0]])
+        return min(1.0, c)
+
     def accuracy(self, X, labels):
         pred = self.logits(X).argmax(dim=1).to(torch.int32) + 1
         return float((pred == labels).float().mean())
