@@ -710,7 +710,74 @@ def bench_learned(args, torch, edm, synth):
 
 
 def bench_twokernel(args, torch, edm, synth):
-    raise SystemExit("the two-kernel workload needs the materialised-distance form")
+    """The paper's two-kernel kNN (distance matrix in HBM, then per-row top-k)
+    against the fused scan.  Part 1, the paper's kNN breakdown: one series of
+    L = 10^4 samples, E = 1..20, Tp = 0, k = E+1, one table per E (HIP-event
+    time per kernel family, median of the timed repetitions).  Part 2, the
+    calcium-like 10000 x 2000 step (sweep + full cross map) in the two-kernel
+    form next to the plain fused form."""
+    torch.cuda.set_device(0)
+    ctx = edm.Context(device=0)
+    X = synth.logistic_network(seed=7, N=4, L=10000)[0]
+    x = torch.from_numpy(X[0].copy()).cuda()
+    L = X.shape[1]
+    reps = max(1, args.steps)
+    rows = []
+    for E in range(1, 21):
+        m = L - (E - 1)
+        rec = {"E": E, "m": m}
+        for fname, form in (("two_kernel", edm.EDM_FORM_TWO_KERNEL), ("fused", edm.EDM_FORM_PLAIN),
+                            ("chosen", edm.EDM_FORM_CHOSEN)):
+            ctx.set_form(form)
+            for _ in range(max(1, args.warmup)):
+                edm.edm_knn(x, E, 1, 0, want_dist=False, ctx=ctx)
+            ctx.sync()
+            per = []
+            for _ in range(reps):
+                ctx.set_timing(True)
+                edm.edm_knn(x, E, 1, 0, want_dist=False, ctx=ctx)
+                per.append(ctx.timing())
+                ctx.set_timing(False)
+            fams = {f for t in per for f, (ms, n) in t.items() if n}
+            rec[fname] = {f: float(np.median([t[f][0] for t in per])) for f in fams}
+        d_ms = rec["two_kernel"]["distances"]
+        t_ms = rec["two_kernel"]["row_topk"]
+        rec["distances_GBps_written"] = 4.0 * m * m / (d_ms / 1e3) / 1e9
+        rec["distances_Tops"] = 3.0 * E * m * m / (d_ms / 1e3) / 1e12
+        rec["row_topk_GBps_read"] = 4.0 * m * m / (t_ms / 1e3) / 1e9
+        rec["fused_over_two_kernel"] = (d_ms + t_ms) / sum(rec["fused"].values())
+        rows.append(rec)
+    ctx.set_form(edm.EDM_FORM_PLAIN)
+    out = {"metric": "kNN table time per E, two-kernel (paper) vs fused, 1 GPU",
+           "unit": "ms", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "one logistic-network series, L=10000, E=1..20, Tp=0, k=E+1"},
+           "per_E": rows}
+    # Part 2: the headline step in the two-kernel form.
+    wl = CALCIUM
+    Xc, _ = synth.calcium_like(seed=wl["seed"], N=wl["N"], L=wl["L"])
+    Xd = torch.from_numpy(Xc).cuda()
+    N = Xc.shape[0]
+    rho = torch.empty((N, N), dtype=torch.float32, device="cuda")
+    steps = max(1, min(args.steps, 2))
+    r2 = run_form(torch, edm, ctx, Xd, rho, wl["E_max"], steps, 1, edm.EDM_FORM_TWO_KERNEL, True)
+    r1 = run_form(torch, edm, ctx, Xd, rho, wl["E_max"], steps, 1, edm.EDM_FORM_PLAIN, True)
+    same = (np.array_equal(r1["rs"].view(np.int32), r2["rs"].view(np.int32))
+            and np.array_equal(r1["Es"], r2["Es"])
+            and np.array_equal(r1["rho"].view(np.int32), r2["rho"].view(np.int32)))
+    fam2 = {f: ms / steps for f, (ms, n) in r2["families"].items() if n}
+    fam1 = {f: ms / steps for f, (ms, n) in r1["families"].items() if n}
+    m_sum = sum(_m(wl["L"], E, 1) ** 2 for E in range(1, 21)) + \
+        sum(_m(wl["L"], E, 0) ** 2 for E in sorted(set(int(e) for e in r2["Es"] if e >= 1)))
+    out["calcium_step"] = {
+        "workload": "calcium-like 10000 x 2000: E sweep 1..20 + full CCM",
+        "two_kernel_ms_per_step": r2["ms_per_step"], "plain_fused_ms_per_step": r1["ms_per_step"],
+        "two_kernel_families_ms": fam2, "plain_families_ms": fam1,
+        "distance_matrix_bytes_per_step": 4.0 * N * m_sum,
+        "distances_GBps_written": 4.0 * N * m_sum / (fam2["distances"] / 1e3) / 1e9,
+        "row_topk_GBps_read": 4.0 * N * m_sum / (fam2["row_topk"] / 1e3) / 1e9,
+        "bit_identical": bool(same), "steps": steps}
+    ctx.close()
+    return out
 
 
 if __name__ == "__main__":

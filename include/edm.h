@@ -63,8 +63,22 @@ typedef struct edm_ctx edm_ctx;
  *                   samples) a BF16 matrix-core estimate of every key filters
  *                   the candidates; the ones that may enter a top-k list are
  *                   re-ranked with the exact float32 key.
- * Tables, rho and E_opt are bit-identical across the three forms. */
-typedef enum { EDM_FORM_PLAIN = 0, EDM_FORM_CHOSEN = 1, EDM_FORM_BATCHED = 2 } edm_form;
+ * EDM_FORM_TWO_KERNEL: the paper's own form of the kNN step (Section 3.3):
+ *                   Algorithm 1 writes each library's whole distance matrix
+ *                   (float32 keys, m x m) to device memory, then Algorithm 2
+ *                   selects the k smallest of every row.  Used by edm_knn,
+ *                   edm_simplex_sweep, edm_ccm, edm_sweep_ccm and
+ *                   edm_select_E in place of the fused scan; the matrices of
+ *                   up to 2 GiB of libraries at a time (at least one) live
+ *                   in a context buffer (EDM_E_NOMEM beyond the workspace
+ *                   limit).  Batched plans treat it as EDM_FORM_PLAIN.
+ * Tables, rho and E_opt are bit-identical across the forms. */
+typedef enum {
+  EDM_FORM_PLAIN = 0,
+  EDM_FORM_CHOSEN = 1,
+  EDM_FORM_BATCHED = 2,
+  EDM_FORM_TWO_KERNEL = 3
+} edm_form;
 
 enum {
   EDM_OK = 0,
@@ -91,6 +105,17 @@ int edm_ctx_create(edm_ctx **ctx, void *hip_stream);
 
 /* Select the arithmetic form (edm_form) for later calls. */
 int edm_ctx_set_form(edm_ctx *ctx, int form);
+
+/* Exclusion radius r >= 0 of the neighbour search for later calls on ctx
+ * (default 0): candidates q with |q - p| <= r are never neighbours of query
+ * p (r = 0 excludes only q = p, the method of Section 2.1 step 2; a larger
+ * r is a Theiler window, which the paper does not use).  A table needs
+ * nq - 1 - 2r >= k (edm_knn returns EDM_E_SHORT otherwise; in sweeps and
+ * cross maps such an E or pair is NaN).  With r > 0, edm_simplex_sweep,
+ * edm_ccm and edm_sweep_ccm run the per-E scan of EDM_FORM_PLAIN (or the
+ * two-kernel form) whatever the form, and edm_ccm_plan_create returns
+ * EDM_E_ARG.  Returns EDM_E_ARG for r < 0 or r > EDM_L_MAX. */
+int edm_ctx_set_exclusion_radius(edm_ctx *ctx, int32_t r);
 
 /* Wait for the context's stream.  Returns EDM_E_HIP for an asynchronous
  * kernel error and EDM_E_NONFINITE when a kernel flagged a non-finite input
@@ -198,6 +223,24 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl,
             int64_t ldx, const float *Y, const int64_t *Ly, int64_t Nt,
             int64_t ldy, const int32_t *E_tgt, int32_t tau, int32_t Tp,
             float *rho);
+
+/* Cross mapping on library subsamples: the convergence test of CCM (the
+ * skill of a causal pair grows with the library size; the criterion Section
+ * 2.1's method rests on, which the paper does not run).  Library x (float32
+ * [L]) is embedded at E; subsample s is a set of candidate points, the host
+ * int32 indices sets[set_off[s] .. set_off[s+1]), strictly ascending, in
+ * [0, nq) with nq = L - (E-1)*tau - Tp.  Every query p in [0, nq) takes its
+ * k = E+1 nearest neighbours inside the set (excluding |q - p| <= r, the
+ * context's exclusion radius, and ties to the lower index), weights as
+ * Section 2.1 step 3, and each target is predicted over all nq queries.
+ * Y     : float32 [Nt][ldy] targets, ldy >= L, read on the library's time axis
+ * sets, set_off : (host) int32 [set_off[S]], int64 [S+1] with set_off[0] = 0
+ * idx   : int32 [S][nq][k] the subsamples' tables, or NULL
+ * rho   : float32 [S][Nt], NaN where a side is constant
+ * Every set needs at least k + 2r + 1 members (EDM_E_SHORT otherwise). */
+int edm_ccm_subsample(edm_ctx *ctx, const float *x, int64_t L, const float *Y, int64_t Nt,
+                      int64_t ldy, int32_t E, int32_t tau, int32_t Tp, const int32_t *sets,
+                      const int64_t *set_off, int64_t S, int32_t *idx, float *rho);
 
 /* The method's pipeline in one call (Section 3.4): the simplex E sweep of
  * every series (Tp = 1, E = 1..E_max) picks each series' E*, then every

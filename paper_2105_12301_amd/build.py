@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libedm.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("EDM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["edm_api.hip", "knn.hip", "sweep_multi.hip", "gram.hip", "fixup.hip", "lookup.hip", "misc.hip", "net.hip", "plan.hip"]
+SOURCES = ["edm_api.hip", "knn.hip", "sweep_multi.hip", "gram.hip", "fixup.hip", "lookup.hip", "misc.hip", "net.hip", "plan.hip", "twokernel.hip", "subsample.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -27,7 +27,9 @@ COMMON = [
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
 ]
 # Per-file extras: the neighbour key must be evaluated without contraction.
-EXTRA = {"knn.hip": ["-ffp-contract=off"], "sweep_multi.hip": ["-ffp-contract=off"], "gram.hip": ["-ffp-contract=off"], "fixup.hip": ["-ffp-contract=off"]}
+EXTRA = {"knn.hip": ["-ffp-contract=off"], "sweep_multi.hip": ["-ffp-contract=off"], "gram.hip": ["-ffp-contract=off"], "fixup.hip": ["-ffp-contract=off"],
+         "twokernel.hip": ["-ffp-contract=off"],
+         "subsample.hip": ["-ffp-contract=off"]}
 
 
 def _hipcc() -> str:

@@ -15,10 +15,13 @@ struct edm_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   int form = EDM_FORM_PLAIN;
+  int32_t excl = 0;            // exclusion radius of the neighbour search (0: self only)
   std::string err;
   char *ws = nullptr;          // device workspace
   size_t ws_bytes = 0;
   int *status = nullptr;       // device status word
+  float *dmat = nullptr;       // distance matrices of the two-kernel form
+  size_t dmat_bytes = 0;
   char *pinned = nullptr;      // host staging buffer
   size_t pinned_bytes = 0;
   hipEvent_t pinned_ready = nullptr;  // recorded after the last copy out of `pinned`

@@ -107,6 +107,43 @@ int check_ctx(edm_ctx *ctx) {
   return EDM_OK;
 }
 
+// The exact kNN scan of one E for `nslots` libraries: the fused kernel, or in
+// EDM_FORM_TWO_KERNEL the paper's distance matrix + row selection, with the
+// matrices of up to kTwoKernelPassBytes of libraries per pass in ctx->dmat.
+constexpr size_t kTwoKernelPassBytes = size_t(2) << 30;
+
+int knn_exact(edm_ctx *ctx, const edm::KnnArgs &a, int nslots, int64_t L_max) {
+  if (ctx->form != EDM_FORM_TWO_KERNEL) {
+    EDM_HIP(ctx, edm::launch_knn(a, nslots, L_max, ctx->stream));
+    return EDM_OK;
+  }
+  if (nslots <= 0) return EDM_OK;
+  const int64_t m_max = L_max - static_cast<int64_t>(a.E - 1) * a.tau - a.Tp;
+  if (m_max < 1) return EDM_OK;
+  const int64_t ldd = edm::two_kernel_ld(m_max);
+  const size_t per_slot = sizeof(float) * static_cast<size_t>(ldd) * static_cast<size_t>(ldd);
+  int per_pass = static_cast<int>(std::max<size_t>(1, std::min<size_t>(kTwoKernelPassBytes / per_slot, nslots)));
+  const size_t want = per_slot * static_cast<size_t>(per_pass);
+  if (want > workspace_limit())
+    return set_err(ctx, EDM_E_NOMEM, "distance matrix exceeds EDM_WORKSPACE_LIMIT");
+  if (want > ctx->dmat_bytes) {
+    EDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->dmat) {
+      EDM_HIP(ctx, hipFree(ctx->dmat));
+      ctx->dmat = nullptr;
+      ctx->dmat_bytes = 0;
+    }
+    if (hipMalloc(reinterpret_cast<void **>(&ctx->dmat), want) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->dmat = nullptr;
+      return set_err(ctx, EDM_E_NOMEM, "distance matrix allocation of " + std::to_string(want) + " bytes failed");
+    }
+    ctx->dmat_bytes = want;
+  }
+  EDM_HIP(ctx, edm::launch_knn_two_kernel(a, nslots, L_max, ctx->dmat, ldd, per_pass, ctx->stream));
+  return EDM_OK;
+}
+
 namespace {
 thread_local edm_ctx *g_timed = nullptr;  // context whose launches are being timed
 
@@ -196,9 +233,17 @@ int edm_ctx_create(edm_ctx **out, void *hip_stream) {
 
 int edm_ctx_set_form(edm_ctx *ctx, int form) {
   EDM_RC(check_ctx(ctx));
-  if (form != EDM_FORM_PLAIN && form != EDM_FORM_CHOSEN && form != EDM_FORM_BATCHED)
+  if (form != EDM_FORM_PLAIN && form != EDM_FORM_CHOSEN && form != EDM_FORM_BATCHED &&
+      form != EDM_FORM_TWO_KERNEL)
     return set_err(ctx, EDM_E_ARG, "unknown form");
   ctx->form = form;
+  return EDM_OK;
+}
+
+int edm_ctx_set_exclusion_radius(edm_ctx *ctx, int32_t r) {
+  EDM_RC(check_ctx(ctx));
+  if (r < 0 || r > EDM_L_MAX) return set_err(ctx, EDM_E_ARG, "exclusion radius must be in 0..EDM_L_MAX");
+  ctx->excl = r;
   return EDM_OK;
 }
 
@@ -252,6 +297,7 @@ void edm_ctx_destroy(edm_ctx *ctx) {
   for (hipEvent_t e : ctx->spare_events) (void)hipEventDestroy(e);
   ctx->spare_events.clear();
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->dmat) (void)hipFree(ctx->dmat);
   if (ctx->status) (void)hipFree(ctx->status);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->pinned_ready) (void)hipEventDestroy(ctx->pinned_ready);
@@ -275,8 +321,10 @@ int edm_knn(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau, int
   const int rc = edm::check_knn(x, L, E, tau, Tp, k, idx, msg);
   if (rc != EDM_OK) return set_err(ctx, rc, msg);
   EDM_RC(check_ctx(ctx));
+  if (edm::n_query(L, E, tau, Tp) - 1 - 2 * static_cast<int64_t>(ctx->excl) < (k ? k : E + 1))
+    return set_err(ctx, EDM_E_SHORT, "series too short for k neighbours outside the exclusion radius");
   if (ctx->form == EDM_FORM_CHOSEN && tau == 1 && (k == 0 || k == E + 1) && dist == nullptr &&
-      E >= edm::kGramEMin && L <= edm::kGramLMax) {
+      E >= edm::kGramEMin && L <= edm::kGramLMax && ctx->excl == 0) {
     // Chosen form: the table of one E through the matrix-core filter (the
     // filtered group scan in table mode; the group's other lists stay idle).
     const int64_t nq = L - (E - 1) - Tp;
@@ -315,14 +363,14 @@ int edm_knn(edm_ctx *ctx, const float *x, int64_t L, int32_t E, int32_t tau, int
   a.tau = tau;
   a.Tp = Tp;
   a.k = k ? k : E + 1;
+  a.excl = ctx->excl;
   a.idx = idx;
   a.dist = dist;
   a.w = w;
   a.tbl_stride = 0;
   a.mom = nullptr;
   a.status = ctx->status;
-  EDM_HIP(ctx, edm::launch_knn(a, 1, L, ctx->stream));
-  return EDM_OK;
+  return knn_exact(ctx, a, 1, L);
 }
 
 int edm_lookup(edm_ctx *ctx, const int32_t *idx, const float *w, int64_t nq, int32_t k, int32_t E,
@@ -370,7 +418,8 @@ int edm_simplex_sweep(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N,
   if (N > INT32_MAX) return set_err(ctx, EDM_E_ARG, "too many series");
   const int64_t L_max = *std::max_element(L, L + N);
   const int32_t mom_blocks = static_cast<int32_t>((L_max + edm::kKnnThreads - 1) / edm::kKnnThreads);
-  const bool batched = (ctx->form == EDM_FORM_CHOSEN || ctx->form == EDM_FORM_BATCHED) && tau == 1;
+  const bool batched =
+      (ctx->form == EDM_FORM_CHOSEN || ctx->form == EDM_FORM_BATCHED) && tau == 1 && ctx->excl == 0;
   const bool gram = batched && ctx->form == EDM_FORM_CHOSEN && E_max >= edm::kGramEMin &&
                     L_max <= edm::kGramLMax;
   const int64_t g_ld = edm::gram_ld(L_max);
@@ -430,14 +479,15 @@ int edm_simplex_sweep(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N,
     a.tau = tau;
     a.Tp = Tp;
     a.k = E + 1;
+    a.excl = ctx->excl;
     a.mom = mom;
     a.mom_blocks = mom_blocks;
     a.E_max = E_max;
     a.status = ctx->status;
-    EDM_HIP(ctx, edm::launch_knn(a, static_cast<int>(N), L_max, ctx->stream));
+    EDM_RC(knn_exact(ctx, a, static_cast<int>(N), L_max));
   }
   }
-  EDM_HIP(ctx, edm::launch_sweep_finalize(mom, mom_blocks, L_dev, N, E_max, tau, Tp, nullptr, rho,
+  EDM_HIP(ctx, edm::launch_sweep_finalize(mom, mom_blocks, L_dev, N, E_max, tau, Tp, ctx->excl, nullptr, rho,
                                           E_opt, ctx->stream));
   return EDM_OK;
 }
@@ -480,7 +530,7 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
     tbl_bytes = std::max(tbl_bytes, static_cast<size_t>(m1 + 1) * (E + 1) * 8 * static_cast<size_t>(N));
   }
   const size_t off_tbl = plan.take(tbl_bytes);
-  bool fused = (ctx->form == EDM_FORM_CHOSEN) && tau == 1 && plan.bytes <= workspace_limit();
+  bool fused = (ctx->form == EDM_FORM_CHOSEN) && tau == 1 && ctx->excl == 0 && plan.bytes <= workspace_limit();
   if (fused && ws_reserve(ctx, plan.bytes) != EDM_OK) fused = false;  // too large to allocate
   if (!fused) {  // the sweep, then the cross map at the selected E (Tp = 0)
     EDM_RC(edm_simplex_sweep(ctx, X, L, N, ldx, E_max, tau, 1, rho_sweep, E_opt));
@@ -513,7 +563,7 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
     EDM_HIP(ctx, edm::launch_gram_prep(a, static_cast<int>(N), L_max, ctx->stream));
   }
   EDM_HIP(ctx, edm::launch_sweep_multi(a, static_cast<int>(N), L_max, ctx->stream));
-  EDM_HIP(ctx, edm::launch_sweep_finalize(mom, mom_blocks, L_dev, N, E_max, 1, 1, nullptr, rho_sweep,
+  EDM_HIP(ctx, edm::launch_sweep_finalize(mom, mom_blocks, L_dev, N, E_max, 1, 1, 0, nullptr, rho_sweep,
                                           E_opt, ctx->stream));
 
   // Targets by their selected E (Section 3.4).
@@ -608,7 +658,8 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
   const size_t off_tbl = plan.take(0);
   // Table bytes of one library: the largest E in use (plain form, one E at a
   // time) or every E in use together (chosen form, one scan per E group).
-  const bool batched = (ctx->form == EDM_FORM_CHOSEN || ctx->form == EDM_FORM_BATCHED) && tau == 1;
+  const bool batched =
+      (ctx->form == EDM_FORM_CHOSEN || ctx->form == EDM_FORM_BATCHED) && tau == 1 && ctx->excl == 0;
   const bool gram = batched && ctx->form == EDM_FORM_CHOSEN && Lx_max <= edm::kGramLMax;
   const int64_t g_ld = edm::gram_ld(Lx_max);
   // Filter norms and centring constant of one library (chosen form).
@@ -724,7 +775,7 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
     if (bucket[e].empty()) continue;
     const int k = e + 1;
     const int64_t m_max = Lx_max - static_cast<int64_t>(e - 1) * tau - Tp;
-    if (m_max - 1 < k) continue;  // no library is long enough for this E
+    if (m_max - 1 - 2 * static_cast<int64_t>(ctx->excl) < k) continue;  // no library is long enough
     const int64_t tbl_stride = m_max * k;
     int32_t *tbl_idx = reinterpret_cast<int32_t *>(ctx->ws + off_tbl);
     float *tbl_w = reinterpret_cast<float *>(ctx->ws + off_tbl + sizeof(int32_t) * tbl_stride * batch);
@@ -740,11 +791,12 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
       a.tau = tau;
       a.Tp = Tp;
       a.k = k;
+      a.excl = ctx->excl;
       a.idx = tbl_idx;
       a.w = tbl_w;
       a.tbl_stride = tbl_stride;
       a.status = ctx->status;
-      EDM_HIP(ctx, edm::launch_knn(a, static_cast<int>(nb), L_b, ctx->stream));
+      EDM_RC(knn_exact(ctx, a, static_cast<int>(nb), L_b));
       edm::LookupArgs b{};
       b.idx = tbl_idx;
       b.w = tbl_w;
@@ -755,6 +807,7 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
       b.tau = tau;
       b.Tp = Tp;
       b.k = k;
+      b.excl = ctx->excl;
       b.Y = Y;
       b.ldy = ldy;
       b.Ly_dev = Ly_dev;
@@ -767,6 +820,85 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
       EDM_HIP(ctx, edm::launch_lookup(b, static_cast<int>(nb), m_b, ctx->stream));
     }
   }
+  return EDM_OK;
+}
+
+int edm_ccm_subsample(edm_ctx *ctx, const float *x, int64_t L, const float *Y, int64_t Nt,
+                      int64_t ldy, int32_t E, int32_t tau, int32_t Tp, const int32_t *sets,
+                      const int64_t *set_off, int64_t S, int32_t *idx, float *rho) {
+  TimingScope timing_scope(ctx);
+  std::string msg;
+  if (!x) return set_err(ctx, EDM_E_ARG, "NULL library");
+  if (E > EDM_E_MAX) return set_err(ctx, EDM_E_ARG, "E must be <= 20");
+  const int rc = edm::check_embedding(L, E, tau, Tp, E + 1, msg);
+  if (rc != EDM_OK) return set_err(ctx, rc, msg);
+  EDM_RC(check_ctx(ctx));
+  if (S < 0 || Nt < 0) return set_err(ctx, EDM_E_ARG, "S and Nt must be >= 0");
+  if (S > 0 && (!sets || !set_off)) return set_err(ctx, EDM_E_ARG, "NULL subsample sets");
+  if (S > 0 && Nt > 0 && (!Y || !rho)) return set_err(ctx, EDM_E_ARG, "NULL pointer (Y and rho)");
+  if (Nt > 0 && ldy < L) return set_err(ctx, EDM_E_ARG, "ldy shorter than the library");
+  if (S > INT32_MAX) return set_err(ctx, EDM_E_ARG, "too many subsamples");
+  const int64_t m = edm::n_query(L, E, tau, Tp);
+  const int K = E + 1;
+  if (S > 0 && set_off[0] != 0) return set_err(ctx, EDM_E_ARG, "set_off[0] must be 0");
+  for (int64_t s = 0; s < S; ++s) {
+    const int64_t b0 = set_off[s], b1 = set_off[s + 1];
+    if (b1 < b0) return set_err(ctx, EDM_E_ARG, "set_off must be non-decreasing");
+    if (b1 - b0 - (2 * static_cast<int64_t>(ctx->excl) + 1) < K)
+      return set_err(ctx, EDM_E_SHORT, "subsample too small for k neighbours outside the exclusion radius");
+    for (int64_t i = b0; i < b1; ++i) {
+      if (sets[i] < 0 || sets[i] >= m) return set_err(ctx, EDM_E_ARG, "subsample index outside [0, nq)");
+      if (i > b0 && sets[i] <= sets[i - 1]) return set_err(ctx, EDM_E_ARG, "subsample indices must ascend strictly");
+    }
+  }
+  if (S == 0) return EDM_OK;
+  const int64_t n_idx = set_off[S];
+  const int64_t stride = m * K;
+  Plan plan;
+  const size_t off_sets = plan.take(sizeof(int32_t) * static_cast<size_t>(n_idx));
+  const size_t off_off = plan.take(sizeof(int64_t) * static_cast<size_t>(S + 1));
+  const size_t small = plan.bytes;
+  const size_t off_idx = plan.take(idx ? 0 : sizeof(int32_t) * static_cast<size_t>(stride) * S);
+  const size_t off_w = plan.take(sizeof(float) * static_cast<size_t>(stride) * S);
+  if (plan.bytes > workspace_limit()) return set_err(ctx, EDM_E_NOMEM, "subsample tables exceed EDM_WORKSPACE_LIMIT");
+  EDM_RC(ws_reserve(ctx, plan.bytes));
+  std::vector<char> blob(small, 0);
+  std::memcpy(blob.data() + off_sets, sets, sizeof(int32_t) * static_cast<size_t>(n_idx));
+  std::memcpy(blob.data() + off_off, set_off, sizeof(int64_t) * static_cast<size_t>(S + 1));
+  EDM_RC(upload(ctx, blob.data(), small, ctx->ws));
+  edm::KnnArgs a{};
+  a.X = x;
+  a.ldx = L;
+  a.L_uni = L;
+  a.E = E;
+  a.tau = tau;
+  a.Tp = Tp;
+  a.k = K;
+  a.excl = ctx->excl;
+  a.idx = idx ? idx : reinterpret_cast<int32_t *>(ctx->ws + off_idx);
+  a.w = reinterpret_cast<float *>(ctx->ws + off_w);
+  a.tbl_stride = stride;
+  a.status = ctx->status;
+  EDM_HIP(ctx, edm::launch_knn_subsets(a, reinterpret_cast<const int32_t *>(ctx->ws + off_sets),
+                                       reinterpret_cast<const int64_t *>(ctx->ws + off_off),
+                                       static_cast<int>(S), ctx->stream));
+  if (Nt == 0) return EDM_OK;
+  edm::LookupArgs b{};
+  b.idx = a.idx;
+  b.w = a.w;
+  b.tbl_stride = stride;
+  b.Lx_uni = L;
+  b.E = E;
+  b.tau = tau;
+  b.Tp = Tp;
+  b.k = K;
+  b.Y = Y;
+  b.ldy = ldy;
+  b.ntgt = static_cast<int32_t>(Nt);
+  b.rho = rho;
+  b.ldrho = Nt;
+  b.status = ctx->status;
+  EDM_HIP(ctx, edm::launch_lookup(b, static_cast<int>(S), m, ctx->stream));
   return EDM_OK;
 }
 
@@ -884,7 +1016,8 @@ int edm_select_E(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int6
     at[E] = static_cast<int64_t>(ids.size());
     for (int64_t s = 0; s < N; ++s) {
       const int64_t m = L[s] - static_cast<int64_t>(E - 1) * tau - Tp;
-      if (((ch[static_cast<size_t>(s)] >> (E - 1)) & 1u) && m - 1 >= E + 1) ids.push_back(static_cast<int32_t>(s));
+      if (((ch[static_cast<size_t>(s)] >> (E - 1)) & 1u) && m - 1 - 2 * ctx->excl >= E + 1)
+        ids.push_back(static_cast<int32_t>(s));
     }
   }
   at[E_max + 1] = static_cast<int64_t>(ids.size());
@@ -901,13 +1034,15 @@ int edm_select_E(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int6
     a.tau = tau;
     a.Tp = Tp;
     a.k = E + 1;
+    a.excl = ctx->excl;
     a.mom = mom;
     a.mom_blocks = mom_blocks;
     a.E_max = E_max;
     a.status = ctx->status;
-    EDM_HIP(ctx, edm::launch_knn(a, static_cast<int>(n_E), L_max, ctx->stream));
+    EDM_RC(knn_exact(ctx, a, static_cast<int>(n_E), L_max));
   }
-  EDM_HIP(ctx, edm::launch_sweep_finalize(mom, mom_blocks, L_dev, N, E_max, tau, Tp, cand, rho, E_opt, ctx->stream));
+  EDM_HIP(ctx, edm::launch_sweep_finalize(mom, mom_blocks, L_dev, N, E_max, tau, Tp, ctx->excl, cand, rho, E_opt,
+                                          ctx->stream));
   if (n_fallback) *n_fallback = fb;
   return EDM_OK;
 }

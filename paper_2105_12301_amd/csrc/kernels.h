@@ -36,6 +36,7 @@ struct KnnArgs {
   int64_t L_uni;
   const int32_t *lib_ids;    // slot -> row of X (device) or nullptr -> row = slot
   int32_t E, tau, Tp, k;
+  int32_t excl;              // exclusion radius: candidates with |q - p| <= excl are skipped
   int32_t *idx;              // [slot][nq][k] or nullptr
   float *dist;               // [slot][nq][k] or nullptr
   float *w;                  // [slot][nq][k] or nullptr
@@ -136,6 +137,23 @@ hipError_t launch_tables_from_sweep(const KnnArgs &a, int E, int nslots, int64_t
 // `L_max` samples.  Returns a hipError_t.
 hipError_t launch_knn(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t st);
 
+// Tables of one library (a.X, a.L_uni, tau, Tp, E, k = E+1, a.excl) whose
+// candidates are restricted to subsamples: set s holds the ascending member
+// indices sets[off[s] .. off[s+1]) (device), table s goes to a.idx / a.w +
+// s * a.tbl_stride ([m][k]).
+hipError_t launch_knn_subsets(const KnnArgs &a, const int32_t *sets, const int64_t *off, int n_sets,
+                              hipStream_t st);
+
+// The paper's two-kernel form of launch_knn (same outputs): per pass of up to
+// slots_per_pass libraries, the distance matrices [slot][m][ldd] float32 are
+// written to D (Algorithm 1), then each row's k smallest are selected
+// (Algorithm 2) and finished as the fused kernel does.  D must hold
+// slots_per_pass * ldd * ldd floats; ldd = two_kernel_ld(m_max) with
+// m_max = L_max - (E-1)*tau - Tp.
+int64_t two_kernel_ld(int64_t m_max);
+hipError_t launch_knn_two_kernel(const KnnArgs &a, int nslots, int64_t L_max, float *D, int64_t ldd,
+                                 int slots_per_pass, hipStream_t st);
+
 // Batched kNN (tau = 1): one scan per group of E values.  With a.mom set it
 // writes the sweep's per-block co-moments for E = 1..a.E_max; otherwise it
 // writes the tables of every E marked in a.need.  Outputs are bit-identical to
@@ -152,6 +170,7 @@ struct LookupArgs {
   const int64_t *Lx_dev;     // library lengths (device) or nullptr -> Lx_uni
   int64_t Lx_uni;
   int32_t E, tau, Tp, k;
+  int32_t excl;              // exclusion radius of the tables (a table exists iff m-1-2*excl >= k)
   const float *Y;            // targets, row j at Y + j*ldy
   int64_t ldy;
   const int64_t *Ly_dev;     // target lengths (device) or nullptr -> every target long enough
@@ -190,7 +209,7 @@ int lookup_tile_targets(int64_t m);
 // E_opt (smallest E with the largest non-NaN rho).
 // cand: optional per-series bit set of the E values evaluated (nullptr: all).
 hipError_t launch_sweep_finalize(const Mom *mom, int32_t mom_blocks, const int64_t *L_dev,
-                                 int64_t N, int32_t E_max, int32_t tau, int32_t Tp,
+                                 int64_t N, int32_t E_max, int32_t tau, int32_t Tp, int32_t excl,
                                  const uint32_t *cand, float *rho, int32_t *E_opt,
                                  hipStream_t st);
 hipError_t launch_candidates(const float *logits, int64_t N, int32_t E_max, int32_t m_top,

@@ -17,7 +17,8 @@
 //   than with every lane looking at the same candidate.  Every lane still
 //   visits its candidates in ascending q, so a strict "<" keeps equal keys in
 //   index order (ties broken by the lower index), and the self step q = p is
-//   the same step s = p0 for the whole wave.
+//   the same step s = p0 for the whole wave (as is every step of an
+//   exclusion window |q - p| <= r: q - p = s - p0 for every lane).
 // * tau = 1: each lane keeps a sliding window of E + U - 1 samples in
 //   registers and loads one new LDS word per candidate, so the key costs
 //   exactly E subtractions, E multiplies and E adds of float32 VALU work.
@@ -87,7 +88,8 @@ __global__ __launch_bounds__(kKnnThreads) void k_knn(KnnArgs a, int slot0) {
   const int tau = T1 ? 1 : a.tau;
   const int off = (E - 1) * tau;
   const int m = L - off - a.Tp;  // queries = candidates
-  if (m - 1 < K) return;         // infeasible for this series (uniform)
+  const int excl = a.excl;       // exclusion radius: |q - p| <= excl is no candidate
+  if (m - 1 - 2 * excl < K) return;  // infeasible for this series (uniform)
   const int blk0 = static_cast<int>(blockIdx.x) * kKnnThreads;
   if (blk0 >= m) return;
 
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(kKnnThreads) void k_knn(KnnArgs a, int slot0) {
           acc = acc + d * d;
         }
       }
-      topk_offer<K>(qk, qi, acc, q, valid && s != p0);
+      topk_offer<K>(qk, qi, acc, q, valid && abs(s - p0) > excl);
     };
 
     int s = -(kWave - 1);
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(kKnnThreads) void k_knn(KnnArgs a, int slot0) {
               const float d = vp[j] - win[u + j];
               acc = acc + d * d;
             }
-            topk_offer<K>(qk, qi, acc, s + u + lane, s + u != p0);
+            topk_offer<K>(qk, qi, acc, s + u + lane, abs(s + u - p0) > excl);
           }
 #pragma unroll
           for (int j = 0; j < E_T - 1; ++j) win[j] = win[j + kUnroll];

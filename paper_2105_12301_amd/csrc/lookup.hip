@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kThreads) void k_lookup(LookupArgs a, int T, int ns
   const int lib = a.lib_ids ? a.lib_ids[slot] : slot;
   const int64_t Lx = a.Lx_dev ? a.Lx_dev[lib] : a.Lx_uni;
   const int m = static_cast<int>(Lx) - off;
-  if (m - 1 < K) return;  // the table does not exist for this library
+  if (m - 1 - 2 * a.excl < K) return;  // the table does not exist for this library
   const int64_t tbl = static_cast<int64_t>(slot) * a.tbl_stride;
   wave_library<K, TPL>(a, a.idx + tbl, a.w + tbl, lib, Lx, m, vs, cs, tgt, Tn, T, lgT);
 }
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void k_lookup_items(LookupArgs a,
       const int lib = __builtin_amdgcn_readfirstlane(a.item_libs[at + wave]);
       const int64_t Lx = a.Lx_dev ? a.Lx_dev[lib] : a.Lx_uni;
       const int m = static_cast<int>(Lx) - off;
-      if (m - 1 >= K) {
+      if (m - 1 - 2 * a.excl >= K) {
         const int64_t o = a.tbl_off[static_cast<int64_t>(lib) * (EDM_E_MAX + 1) + E];
         if (T >= 16)
           wave_library<K, 4>(a, a.tbl_idx + o, a.tbl_w + o, lib, Lx, m, vs, cs, tgt, Tn, T, lgT);

@@ -12,8 +12,9 @@ namespace {
 // float64 correlation before it is rounded for output.
 __global__ void k_sweep_finalize(const Mom *__restrict__ mom, int32_t mom_blocks,
                                  const int64_t *__restrict__ L, int64_t N, int32_t E_max,
-                                 int32_t tau, int32_t Tp, const uint32_t *__restrict__ cand,
-                                 float *__restrict__ rho, int32_t *__restrict__ E_opt) {
+                                 int32_t tau, int32_t Tp, int32_t excl,
+                                 const uint32_t *__restrict__ cand, float *__restrict__ rho,
+                                 int32_t *__restrict__ E_opt) {
   const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= N) return;
   double best = -__builtin_inf();
@@ -22,7 +23,7 @@ __global__ void k_sweep_finalize(const Mom *__restrict__ mom, int32_t mom_blocks
     const int64_t m = L[s] - static_cast<int64_t>(E - 1) * tau - Tp;
     double r = __builtin_nan("");
     const bool evaluated = cand == nullptr || ((cand[s] >> (E - 1)) & 1u);
-    if (evaluated && m - 1 >= E + 1) {
+    if (evaluated && m - 1 - 2 * excl >= E + 1) {
       const int nb = static_cast<int>((m + kKnnThreads - 1) / kKnnThreads);
       const Mom *base = mom + (s * E_max + (E - 1)) * static_cast<int64_t>(mom_blocks);
       Mom t = base[0];
@@ -98,13 +99,13 @@ unsigned grid_for(int64_t n, int threads) {
 }  // namespace
 
 hipError_t launch_sweep_finalize(const Mom *mom, int32_t mom_blocks, const int64_t *L_dev,
-                                 int64_t N, int32_t E_max, int32_t tau, int32_t Tp,
+                                 int64_t N, int32_t E_max, int32_t tau, int32_t Tp, int32_t excl,
                                  const uint32_t *cand, float *rho, int32_t *E_opt,
                                  hipStream_t st) {
   if (N <= 0) return hipSuccess;
   TimedLaunch timed(EDM_KF_FINALIZE, st);
   hipLaunchKernelGGL(k_sweep_finalize, dim3(grid_for(N, 64)), dim3(64), 0, st, mom, mom_blocks,
-                     L_dev, N, E_max, tau, Tp, cand, rho, E_opt);
+                     L_dev, N, E_max, tau, Tp, excl, cand, rho, E_opt);
   return hipGetLastError();
 }
 

@@ -133,6 +133,7 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
       tn.lookup_wg_per_cu > 16 || tn.lookup_targets < 1 || tn.lookup_targets > edm::kLookupItemMaxTargets)
     return set_err(ctx, EDM_E_ARG, "tune out of range");
   EDM_RC(check_ctx(ctx));
+  if (ctx->excl != 0) return set_err(ctx, EDM_E_ARG, "batched plans need exclusion radius 0");
 
   edm_plan *P = new (std::nothrow) edm_plan();
   if (!P) return set_err(ctx, EDM_E_NOMEM, "out of host memory");

@@ -30,6 +30,7 @@ EDM_E_NONFINITE = -5
 EDM_FORM_PLAIN = 0
 EDM_FORM_CHOSEN = 1
 EDM_FORM_BATCHED = 2
+EDM_FORM_TWO_KERNEL = 3
 E_MAX = 20
 K_MAX = 32
 L_MAX = 32768
@@ -46,7 +47,7 @@ EXPORTS = (
     "edm_net_adam",
     "edm_select_E",
     "edm_tune_default", "edm_ccm_plan_create", "edm_ccm_plan_run", "edm_ccm_plan_destroy",
-    "edm_ctx_set_timing", "edm_ctx_timing",
+    "edm_ctx_set_timing", "edm_ctx_timing", "edm_ctx_set_exclusion_radius", "edm_ccm_subsample",
 )
 
 # kernel families of edm_ctx_timing (include/edm.h, EDM_KF_*)
@@ -115,6 +116,9 @@ def load_library(path: str = LIB_PATH):
         lib.edm_ccm_plan_run.argtypes = [_p, _p, _p, _p, _p]
         lib.edm_ctx_set_timing.argtypes = [_p, ctypes.c_int]
         lib.edm_ctx_timing.argtypes = [_p, _p, _p]
+        lib.edm_ctx_set_exclusion_radius.argtypes = [_p, _i32]
+        lib.edm_ccm_subsample.argtypes = [_p, _p, _i64, _p, _i64, _i64, _i32, _i32, _i32, _p, _p,
+                                          _i64, _p, _p]
         lib.edm_ccm_plan_destroy.argtypes = [_p, _p]
         lib.edm_ccm_plan_destroy.restype = None
         for name in EXPORTS:
@@ -174,6 +178,11 @@ class Context:
     def set_form(self, form: int):
         _check(load_library().edm_ctx_set_form(self._h, int(form)), self._h)
         self.form = int(form)
+
+    def set_exclusion_radius(self, r: int):
+        """Exclusion radius of the neighbour search (edm_ctx_set_exclusion_radius)."""
+        _check(load_library().edm_ctx_set_exclusion_radius(self._h, int(r)), self._h)
+        self.excl = int(r)
 
     def sync(self):
         _check(load_library().edm_sync(self._h), self._h)
@@ -324,6 +333,33 @@ def edm_sweep_ccm(X, lengths=None, E_max: int = E_MAX, tau: int = 1, rho=None,
         _dev_ptr(rho_s, torch.float32, "rho_sweep"), _dev_ptr(E_opt, torch.int32, "E_opt"),
         _dev_ptr(rho, torch.float32, "rho")), ctx.handle)
     return rho_s, E_opt, rho
+
+
+def edm_ccm_subsample(x, Y, E: int, sets, tau: int = 1, Tp: int = 0, want_idx=False,
+                      ctx: Context | None = None):
+    """Cross map of library x on subsamples (the convergence test).
+    sets: sequence of S ascending int index arrays (candidate points).
+    Returns (rho float32 [S][Nt], idx int32 [S][nq][k] or None)."""
+    ctx = ctx or default_context(x.device)
+    if Y.dim() == 1:
+        Y = Y.unsqueeze(0)
+    L = x.shape[0]
+    Nt, ldy = Y.shape
+    S = len(sets)
+    off = np.zeros(S + 1, dtype=np.int64)
+    for s, c in enumerate(sets):
+        off[s + 1] = off[s] + len(c)
+    flat = (np.concatenate([np.asarray(c, dtype=np.int32) for c in sets]) if S and off[-1]
+            else np.zeros(1, dtype=np.int32))
+    flat = np.ascontiguousarray(flat, dtype=np.int32)
+    nq = max(n_query(L, E, tau, Tp), 0)
+    rho = torch.empty((S, Nt), dtype=torch.float32, device=x.device)
+    idx = torch.empty((S, nq, E + 1), dtype=torch.int32, device=x.device) if want_idx else None
+    _check(load_library().edm_ccm_subsample(
+        ctx.handle, _dev_ptr(x, torch.float32, "x"), L, _dev_ptr(Y, torch.float32, "Y"), Nt, ldy,
+        E, tau, Tp, flat.ctypes.data_as(_p), off.ctypes.data_as(_p), S,
+        _dev_ptr(idx, torch.int32, "idx"), _dev_ptr(rho, torch.float32, "rho")), ctx.handle)
+    return rho, idx
 
 
 # ---------------------------------------------------------------- surrogate --
