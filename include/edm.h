@@ -242,6 +242,23 @@ int edm_ccm_subsample(edm_ctx *ctx, const float *x, int64_t L, const float *Y, i
                       int64_t ldy, int32_t E, int32_t tau, int32_t Tp, const int32_t *sets,
                       const int64_t *set_off, int64_t S, int32_t *idx, float *rho);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as edm_simplex_sweep in EDM_FORM_PLAIN (one
+ * fused scan per E, the context's exclusion radius), whatever the context's
+ * form, with no allocation of any kind.  Its scratch (the lengths and the
+ * per-block co-moments, 8 N + 48 N E_max ceil(L_max/256) bytes) lives in a
+ * static device array of 64 MiB per GPU, resolved by edm_ctx_create and held
+ * until the process ends; larger inputs return EDM_E_NOMEM (use
+ * edm_simplex_sweep).  Every call on a GPU shares that array: calls that
+ * overlap in time on one GPU (several contexts or threads) race.  With equal
+ * lengths the call makes no host-to-device copy; otherwise L is copied from
+ * the caller's host array.  Kernel timing (edm_ctx_set_timing) does not
+ * cover this call. */
+int edm_simplex_sweep_noalloc(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N,
+                              int64_t ldx, int32_t E_max, int32_t tau, int32_t Tp,
+                              float *rho, int32_t *E_opt);
+
 /* The method's pipeline in one call (Section 3.4): the simplex E sweep of
  * every series (Tp = 1, E = 1..E_max) picks each series' E*, then every
  * ordered pair is cross-mapped at the target's E* (Tp = 0), the series being

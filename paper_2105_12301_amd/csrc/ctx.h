@@ -46,6 +46,9 @@ size_t workspace_limit();
 int ws_reserve(edm_ctx *ctx, size_t bytes);
 int upload(edm_ctx *ctx, const void *host, size_t bytes, void *dev);
 int check_ctx(edm_ctx *ctx);
+// Resolves this device's copy of the allocation-free entry point's static
+// scratch (once per device; called by edm_ctx_create).
+int noalloc_scratch_init(edm_ctx *ctx);
 
 // While alive, kernel launches of this thread are timed on ctx (when its
 // timing is on); one of these opens every C ABI call that launches kernels.

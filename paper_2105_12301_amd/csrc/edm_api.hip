@@ -220,8 +220,9 @@ int edm_ctx_create(edm_ctx **out, void *hip_stream) {
   if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->stream);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->pinned_ready, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e != hipSuccess) {
-    const int rc = hip_err(nullptr, e, "edm_ctx_create");
+  int rc = e == hipSuccess ? EDM_OK : hip_err(nullptr, e, "edm_ctx_create");
+  if (rc == EDM_OK) rc = noalloc_scratch_init(ctx);
+  if (rc != EDM_OK) {
     if (ctx->status) (void)hipFree(ctx->status);
     if (ctx->pinned_ready) (void)hipEventDestroy(ctx->pinned_ready);
     delete ctx;

@@ -48,6 +48,7 @@ EXPORTS = (
     "edm_select_E",
     "edm_tune_default", "edm_ccm_plan_create", "edm_ccm_plan_run", "edm_ccm_plan_destroy",
     "edm_ctx_set_timing", "edm_ctx_timing", "edm_ctx_set_exclusion_radius", "edm_ccm_subsample",
+    "edm_simplex_sweep_noalloc",
 )
 
 # kernel families of edm_ctx_timing (include/edm.h, EDM_KF_*)
@@ -117,6 +118,7 @@ def load_library(path: str = LIB_PATH):
         lib.edm_ctx_set_timing.argtypes = [_p, ctypes.c_int]
         lib.edm_ctx_timing.argtypes = [_p, _p, _p]
         lib.edm_ctx_set_exclusion_radius.argtypes = [_p, _i32]
+        lib.edm_simplex_sweep_noalloc.argtypes = [_p, _p, _p, _i64, _i64, _i32, _i32, _i32, _p, _p]
         lib.edm_ccm_subsample.argtypes = [_p, _p, _i64, _p, _i64, _i64, _i32, _i32, _i32, _p, _p,
                                           _i64, _p, _p]
         lib.edm_ccm_plan_destroy.argtypes = [_p, _p]
