@@ -505,33 +505,35 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
   if (N > INT32_MAX) return set_err(ctx, EDM_E_ARG, "too many series");
   const int64_t L_max = *std::max_element(L, L + N);
 
-  // Workspace of the fused form: the sweep's lists of every E, and one E's
-  // cross-map tables at a time.
+  // Workspace of the fused form: the sweep's lists and weights of every E,
+  // with one row more per series (query m1 of the cross map): the cross
+  // map's tables are these arrays, completed in place.
   const int32_t mom_blocks = static_cast<int32_t>((L_max + edm::kKnnThreads - 1) / edm::kKnnThreads);
   const bool gram = E_max >= edm::kGramEMin && L_max <= edm::kGramLMax;
   const int64_t g_ld = edm::gram_ld(L_max);
   Plan plan;
   const size_t off_L = plan.take(sizeof(int64_t) * N);
   const size_t off_ids = plan.take(sizeof(int32_t) * N);
+  const size_t off_at = plan.take(sizeof(int32_t) * (EDM_E_MAX + 2));
   const size_t off_mom = plan.take(edm::kMomBytes * static_cast<size_t>(N) * E_max * mom_blocks);
   size_t off_gmu = 0, off_gnrm = 0;
   if (gram) {
     off_gmu = plan.take(sizeof(float) * N);
     off_gnrm = plan.take(sizeof(uint32_t) * static_cast<size_t>(edm::kGramNE) * g_ld * N);
   }
-  std::vector<size_t> off_keep(EDM_E_MAX + 1, 0);
+  std::vector<size_t> off_keep(EDM_E_MAX + 1, 0), off_keepw(EDM_E_MAX + 1, 0);
   std::vector<int64_t> keep_stride(EDM_E_MAX + 1, 0);
-  size_t tbl_bytes = 0;
   for (int E = 1; E <= E_max; ++E) {
-    const int64_t m1 = L_max - E;  // sweep queries at E (Tp = 1)
+    const int64_t m1 = L_max - E;  // sweep queries at E (Tp = 1); the cross map has m1 + 1
     if (m1 > 0) {
-      keep_stride[E] = m1 * (E + 1);
+      keep_stride[E] = (m1 + 1) * (E + 1);
       off_keep[E] = plan.take(sizeof(int32_t) * static_cast<size_t>(keep_stride[E]) * N);
+      off_keepw[E] = plan.take(sizeof(float) * static_cast<size_t>(keep_stride[E]) * N);
     }
-    tbl_bytes = std::max(tbl_bytes, static_cast<size_t>(m1 + 1) * (E + 1) * 8 * static_cast<size_t>(N));
   }
-  const size_t off_tbl = plan.take(tbl_bytes);
-  bool fused = (ctx->form == EDM_FORM_CHOSEN) && tau == 1 && ctx->excl == 0 && plan.bytes <= workspace_limit();
+  // (the device-memory query only when the workspace must grow)
+  bool fused = (ctx->form == EDM_FORM_CHOSEN) && tau == 1 && ctx->excl == 0 &&
+               (plan.bytes <= ctx->ws_bytes || plan.bytes <= workspace_limit());
   if (fused && ws_reserve(ctx, plan.bytes) != EDM_OK) fused = false;  // too large to allocate
   if (!fused) {  // the sweep, then the cross map at the selected E (Tp = 0)
     EDM_RC(edm_simplex_sweep(ctx, X, L, N, ldx, E_max, tau, 1, rho_sweep, E_opt));
@@ -539,8 +541,14 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
   }
   int64_t *L_dev = reinterpret_cast<int64_t *>(ctx->ws + off_L);
   int32_t *ids_dev = reinterpret_cast<int32_t *>(ctx->ws + off_ids);
+  int32_t *at_dev = reinterpret_cast<int32_t *>(ctx->ws + off_at);
   edm::Mom *mom = reinterpret_cast<edm::Mom *>(ctx->ws + off_mom);
-  EDM_RC(upload(ctx, L, sizeof(int64_t) * N, L_dev));
+  // Equal lengths are written on the device: the call then makes no host
+  // transfer and no synchronisation at all (it can be captured in a graph).
+  if (std::all_of(L, L + N, [&](int64_t v) { return v == L[0]; }))
+    EDM_HIP(ctx, edm::launch_fill_i64(L_dev, N, L[0], ctx->stream));
+  else
+    EDM_RC(upload(ctx, L, sizeof(int64_t) * N, L_dev));
 
   edm::KnnArgs a{};
   a.X = X;
@@ -555,6 +563,7 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
   for (int E = 1; E <= E_max; ++E) {
     if (keep_stride[E] == 0) continue;
     a.keepE[E] = reinterpret_cast<int32_t *>(ctx->ws + off_keep[E]);
+    a.keepWE[E] = reinterpret_cast<float *>(ctx->ws + off_keepw[E]);
     a.keep_strideE[E] = keep_stride[E];
   }
   if (gram) {
@@ -567,26 +576,12 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
   EDM_HIP(ctx, edm::launch_sweep_finalize(mom, mom_blocks, L_dev, N, E_max, 1, 1, 0, nullptr, rho_sweep,
                                           E_opt, ctx->stream));
 
-  // Targets by their selected E (Section 3.4).
-  std::vector<int32_t> Eh(static_cast<size_t>(N));
-  EDM_HIP(ctx, hipMemcpyAsync(Eh.data(), E_opt, sizeof(int32_t) * N, hipMemcpyDeviceToHost, ctx->stream));
-  EDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  std::vector<std::vector<int32_t>> bucket(EDM_E_MAX + 1);
-  for (int64_t j = 0; j < N; ++j) {
-    const int e = Eh[static_cast<size_t>(j)];
-    if (e >= 1 && e <= E_max) bucket[e].push_back(static_cast<int32_t>(j));
-  }
-  std::vector<int32_t> ids;
-  std::vector<int64_t> at(EDM_E_MAX + 1, 0);
-  for (int e = 1; e <= EDM_E_MAX; ++e) {
-    at[e] = static_cast<int64_t>(ids.size());
-    ids.insert(ids.end(), bucket[e].begin(), bucket[e].end());
-  }
-  if (!ids.empty()) EDM_RC(upload(ctx, ids.data(), sizeof(int32_t) * ids.size(), ids_dev));
+  // Targets by their selected E (Section 3.4), grouped on the device: every
+  // E is launched, and its kernels exit at once when its bucket is empty.
+  EDM_HIP(ctx, edm::launch_group_by_E(E_opt, N, E_max, at_dev, ids_dev, ctx->stream));
   EDM_HIP(ctx, edm::launch_fill(rho, N * N, __builtin_nanf(""), ctx->stream));
 
   for (int e = 1; e <= E_max; ++e) {
-    if (bucket[e].empty()) continue;
     const int64_t m0 = L_max - (e - 1);  // cross-map queries at e (Tp = 0)
     if (m0 - 1 < e + 1) continue;        // no library is long enough for this E
     edm::KnnArgs t{};
@@ -599,10 +594,12 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
     t.status = ctx->status;
     t.need = 1u << (e - 1);
     t.keepE[e] = a.keepE[e];
+    t.keepWE[e] = a.keepWE[e];
     t.keep_strideE[e] = a.keep_strideE[e];
-    const int64_t stride = m0 * (e + 1);
-    t.idxE[e] = reinterpret_cast<int32_t *>(ctx->ws + off_tbl);
-    t.wE[e] = reinterpret_cast<float *>(ctx->ws + off_tbl + sizeof(int32_t) * stride * N);
+    t.group_at = at_dev;
+    const int64_t stride = a.keep_strideE[e];  // m0 * (e + 1): the kept arrays are the tables
+    t.idxE[e] = a.keepE[e];
+    t.wE[e] = a.keepWE[e];
     t.strideE[e] = stride;
     EDM_HIP(ctx, edm::launch_tables_from_sweep(t, e, static_cast<int>(N), L_max, ctx->stream));
     edm::LookupArgs b{};
@@ -617,12 +614,12 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
     b.Y = X;
     b.ldy = ldx;
     b.Ly_dev = L_dev;
-    b.tgt_ids = ids_dev + at[e];
-    b.ntgt = static_cast<int32_t>(bucket[e].size());
+    b.bucket_ids = ids_dev;
+    b.bucket_at = at_dev;
     b.rho = rho;
     b.ldrho = N;
     b.status = ctx->status;
-    EDM_HIP(ctx, edm::launch_lookup(b, static_cast<int>(N), m0, ctx->stream));
+    EDM_HIP(ctx, edm::launch_lookup_bucket(b, static_cast<int>(N), m0, N, ctx->stream));
   }
   return EDM_OK;
 }

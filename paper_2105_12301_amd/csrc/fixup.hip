@@ -7,8 +7,9 @@
 // Tp = 0 has m0 = m1 + 1 of each: one more candidate, index m1, and one more
 // query, p = m1.  For p < m1 the Tp = 0 list is therefore the sweep's list
 // with candidate m1 offered last; it has the largest index, so a strict "<"
-// puts it after equal keys, exactly where a full scan would.  Query p = m1
-// is scanned in full.  A series with no sweep list at E (m1 - 1 < E + 1) but
+// puts it after equal keys, exactly where a full scan would (and where it
+// does not enter, the sweep's weights are the table's).  Query p = m1 is
+// scanned in full.  A series with no sweep list at E (m1 - 1 < E + 1) but
 // a defined cross map (m0 - 1 >= E + 1) has every query scanned.
 // Keys are the float32 sums of Algorithm 1 (contraction off), so the tables
 // are bit-identical to the scans'.
@@ -42,34 +43,61 @@ __device__ __forceinline__ void stage(const KnnArgs &a, int row, int L, float *x
   __syncthreads();
 }
 
-// Queries p < m1: one thread per query.
+// Queries p < m1: one thread per query, the series read from global memory
+// (L2).  The sweep's list is the cross map's unless candidate m1 enters it,
+// that is unless key(p, m1) < key(p, last entry); then the list and the
+// weights the sweep kept are the table row (the weights depend only on the
+// query and its neighbours), and when the table is the kept array itself the
+// row is left as it is.  Otherwise every key is recomputed, m1 is inserted
+// and the row is rewritten (the kept entries are read before).
 template <int E>
 __global__ __launch_bounds__(256) void k_fix_from_sweep(KnnArgs a, int slot0) {
   constexpr int K = E + 1;
-  extern __shared__ float fx_xs[];
+  if (a.group_at && a.group_at[E + 1] == a.group_at[E]) return;  // no target of this E
   const int row = slot0 + static_cast<int>(blockIdx.y);
   const int L = static_cast<int>(a.L_dev ? a.L_dev[row] : a.L_uni);
   const int m1 = L - E;
   if (m1 - 1 < K) return;  // no sweep list: k_scan_queries covers this series
-  const int p0 = static_cast<int>(blockIdx.x) * 256;
-  if (p0 >= m1) return;
-  stage(a, row, L, fx_xs);
-  const int p = p0 + static_cast<int>(threadIdx.x);
+  const int p = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
   if (p >= m1) return;
-  const int32_t *kp = a.keepE[E] + static_cast<int64_t>(row) * a.keep_strideE[E] +
-                      static_cast<int64_t>(p) * K;
-  float qk[K];
-  int qi[K];
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    qi[i] = kp[i];
-    qk[i] = canon_key<E>(fx_xs, p, qi[i]);
-  }
-  slice_insert<0, K, K>(qk, qi, canon_key<E>(fx_xs, p, m1), m1);
+  const float *__restrict__ x = a.X + static_cast<int64_t>(row) * a.ldx;
+  const int64_t ko = static_cast<int64_t>(row) * a.keep_strideE[E] + static_cast<int64_t>(p) * K;
+  const int32_t *__restrict__ kp = a.keepE[E] + ko;
   float vp[E];
 #pragma unroll
-  for (int j = 0; j < E; ++j) vp[j] = fx_xs[p + j];
-  finish_list<E, 0, K, E>(a, row, p, L, 0, a.need, vp, qi, fx_xs);
+  for (int j = 0; j < E; ++j) vp[j] = x[p + j];
+  auto key = [&](int q) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const float d = vp[j] - x[q + j];
+      acc = acc + d * d;
+    }
+    return acc;
+  };
+  const float k_m1 = key(m1);
+  if (a.keepWE[E] && !(k_m1 < key(kp[K - 1]))) {
+    // the kept row is the table row: nothing to do when the table is the
+    // kept array itself (one extra row per slot for query m1), else a copy
+    if (a.idxE[E] == a.keepE[E] && a.wE[E] == a.keepWE[E] && a.strideE[E] == a.keep_strideE[E]) return;
+    const int64_t base = static_cast<int64_t>(row) * a.strideE[E] + static_cast<int64_t>(p) * K;
+    const float *__restrict__ kw = a.keepWE[E] + ko;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      a.idxE[E][base + i] = kp[i];
+      a.wE[E][base + i] = kw[i];
+    }
+    return;
+  }
+  // m1 enters after every entry whose key is at most its own (it has the
+  // largest index) and pushes the last entry out.
+  int pos = 0;
+#pragma unroll 1
+  for (int i = 0; i < K; ++i) pos += key(kp[i]) <= k_m1 ? 1 : 0;
+  int qi[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) qi[i] = i < pos ? kp[i] : (i == pos ? m1 : kp[i - 1 < 0 ? 0 : i - 1]);
+  finish_list<E, 0, K, E>(a, row, p, L, 0, a.need, vp, qi, x);
 }
 
 // Full scans, one query per wave: the lanes walk the candidates in ascending
@@ -81,6 +109,7 @@ template <int E>
 __global__ __launch_bounds__(256) void k_scan_queries(KnnArgs a, int slot0) {
   constexpr int K = E + 1;
   extern __shared__ float fx_xs[];
+  if (a.group_at && a.group_at[E + 1] == a.group_at[E]) return;  // no target of this E
   const int row = slot0 + static_cast<int>(blockIdx.y);
   const int L = static_cast<int>(a.L_dev ? a.L_dev[row] : a.L_uni);
   const int m0 = L - (E - 1), m1 = m0 - 1;
@@ -140,19 +169,16 @@ using FixFn = hipError_t (*)(const KnnArgs &, int, int64_t, hipStream_t);
 template <int E>
 hipError_t launch_fix(const KnnArgs &a, int nslots, int64_t L_max, hipStream_t st) {
   const size_t shm = static_cast<size_t>(L_max) * sizeof(float);
-  const void *f1 = reinterpret_cast<const void *>(&k_fix_from_sweep<E>);
   const void *f2 = reinterpret_cast<const void *>(&k_scan_queries<E>);
   if (shm > 65536) {
-    hipError_t e = hipFuncSetAttribute(f1, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm));
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(f2, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm));
+    hipError_t e = hipFuncSetAttribute(f2, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm));
     if (e != hipSuccess) return e;
   }
   const unsigned gx = static_cast<unsigned>((L_max + 255) / 256);
   constexpr int kMaxY = 32768;
   for (int s0 = 0; s0 < nslots; s0 += kMaxY) {
     const unsigned ny = static_cast<unsigned>(nslots - s0 < kMaxY ? nslots - s0 : kMaxY);
-    hipLaunchKernelGGL(k_fix_from_sweep<E>, dim3(gx, ny), dim3(256), shm, st, a, s0);
+    hipLaunchKernelGGL(k_fix_from_sweep<E>, dim3(gx, ny), dim3(256), 0, st, a, s0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_queries<E>, dim3(1, ny), dim3(256), shm, st, a, s0);

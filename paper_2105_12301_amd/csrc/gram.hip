@@ -377,12 +377,18 @@ __device__ __forceinline__ Mom finish_round(const KnnArgs &a, int row, int p, in
       }
     } else {
       int32_t *keep = hi ? a.keepE[E1] : a.keepE[E0];
-      if (keep) {  // sweep mode: keep the sorted list for a later cross map
-        int32_t *kp = keep + static_cast<int64_t>(row) * (hi ? a.keep_strideE[E1] : a.keep_strideE[E0]) +
-                      static_cast<int64_t>(p) * K;
+      if (keep) {  // sweep mode: keep the sorted list (and weights) for a later cross map
+        const int64_t ko = static_cast<int64_t>(row) * (hi ? a.keep_strideE[E1] : a.keep_strideE[E0]) +
+                           static_cast<int64_t>(p) * K;
+        float *keepw = hi ? a.keepWE[E1] : a.keepWE[E0];
 #pragma unroll
         for (int i = 0; i < KM; ++i)
-          if (i < KM - 1 || hi || E1 == E0) kp[i] = q[i];
+          if (i < KM - 1 || hi || E1 == E0) keep[ko + i] = q[i];
+        if (keepw) {
+#pragma unroll
+          for (int i = 0; i < KM; ++i)
+            if (i < KM - 1 || hi || E1 == E0) keepw[ko + i] = static_cast<float>(D[i] * inv);
+        }
       }
       const int o_off = (E - 1) + Tp;
       double yh = 0.0;

@@ -68,8 +68,15 @@ struct KnnArgs {
   // Sweep mode: when keepE[E] is set, the sorted neighbour list of every
   // query at E is also written there ([slot][m][E+1] int32, slot stride
   // keep_strideE[E]) for a later cross map (launch_tables_from_sweep).
+  // keepWE[E] (same layout, float32, or nullptr): the list's normalised
+  // weights, which are the cross map's weights wherever its list is the same.
   int32_t *keepE[EDM_E_MAX + 1];
+  float *keepWE[EDM_E_MAX + 1];
   int64_t keep_strideE[EDM_E_MAX + 1];
+  // Cross map with the targets grouped on the device (launch_group_by_E):
+  // bucket offsets [EDM_E_MAX + 2]; a table kernel of dimension E exits when
+  // bucket E is empty.  nullptr: every launched table is built.
+  const int32_t *group_at;
 };
 
 // Work item of the persistent table kernel: E group and query block of a row.
@@ -189,12 +196,15 @@ struct LookupArgs {
   const int32_t *bucket_ids;
   const int32_t *bucket_at;
   const int32_t *item_libs;  // library ids of the work items' groups
+  // Grid kernel with the bucket on the device (tbl_off == nullptr and
+  // bucket_at set): the targets are bucket_ids[bucket_at[E] ..
+  // bucket_at[E+1]) and ntgt is ignored.
 };
 
 // Lookups of the work list of one E: persistent (wg_per_cu * n_cu
 // workgroups pulling items from *counter) or one workgroup per item
 // (wg_per_cu = 0).
-// lds_floats: dynamic LDS per workgroup (max over items of T * m).
+// lds_floats: dynamic LDS per workgroup (max over items of lookup_tile_floats).
 hipError_t launch_lookup_items(const LookupArgs &a, int E, const LookupItem *items, int n_items,
                                int *counter, int64_t lds_floats, int wg_per_cu, int n_cu,
                                hipStream_t st);
@@ -204,6 +214,9 @@ hipError_t launch_lookup(const LookupArgs &a, int nslots, int64_t m_max, hipStre
 // Targets per staged lookup tile for a window of m samples: the largest of
 // 16, 8, 4, 2, 1 whose tile fits the lookup kernels' 160 KB of LDS.
 int lookup_tile_targets(int64_t m);
+// LDS floats of a staged tile of T targets over a window of m samples
+// (padded rows).
+int64_t lookup_tile_floats(int T, int64_t m);
 
 // Sweep epilogue: merge the per-block moments into rho[N][E_max] and pick
 // E_opt (smallest E with the largest non-NaN rho).
@@ -216,6 +229,16 @@ hipError_t launch_candidates(const float *logits, int64_t N, int32_t E_max, int3
                              float min_conf, uint32_t *cand, hipStream_t st);
 
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
+hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t st);
+// Stable grouping of N targets by E (counting sort on the device): at[e] is
+// the first position of bucket e (e = 0 holds E outside 1..E_max), at[E_max+1
+// .. EDM_E_MAX+1] = N, ids[at[e] ..] the targets of E in ascending order.
+hipError_t launch_group_by_E(const int32_t *E, int64_t N, int32_t E_max, int32_t *at, int32_t *ids,
+                             hipStream_t st);
+// launch_lookup with the bucket on the device: a.bucket_ids / a.bucket_at
+// set, n_tgt_max bounds the bucket (for the tile size).
+hipError_t launch_lookup_bucket(const LookupArgs &a, int nslots, int64_t m_max, int64_t n_tgt_max,
+                                hipStream_t st);
 hipError_t launch_embed(const float *x, int64_t L, int32_t E, int32_t tau, float *out,
                         int *status, hipStream_t st);
 

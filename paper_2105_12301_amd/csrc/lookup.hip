@@ -4,10 +4,12 @@
 // Data layout.  A workgroup stages a tile of T targets (T in 1, 2, 4, 8, 16,
 // as many as fit 160 KB of LDS for the window) over the window that its
 // libraries' tables can touch, interleaved: vs[e][t] = y_t[off + e] - c_t with
-// c_t = y_t[off], off = (E-1)*tau + Tp.  One neighbour index q then addresses
-// the T targets' samples as one contiguous LDS segment, so a wave reads them
-// with one 128-, 64- or 32-bit access per lane instead of T scattered 32-bit
-// gathers.
+// c_t = y_t[off], off = (E-1)*tau + Tp, rows S = tile_stride(T) floats apart.
+// One neighbour index q then addresses the T targets' samples as one
+// contiguous LDS segment, so a wave reads them with one 128-, 64- or 32-bit
+// access per lane instead of T scattered 32-bit gathers.  (Rows padded to
+// T + 4 floats, which spreads the random rows over more bank offsets, made
+// the headline lookups 5 % slower on gfx950; the rows are unpadded.)
 //
 // Lane layout.  A wave walks one library's table: lane = 4 g + s, query group
 // g = 0..15 handles the queries p = g, g + 16, g + 32, ... and sub-lane s the
@@ -44,10 +46,14 @@ namespace edm {
 namespace {
 
 constexpr int kGroups = 16;                  // query groups per wave
+constexpr int kXcds = 8;                     // accelerator dies (separate L2 caches) of the chip
+constexpr int kTileCols = 16;                // tile columns per library group (device buckets)
 constexpr int kSubs = 4;                     // lanes per query group
 constexpr int kWaves = kLookupItemLibs;      // libraries per workgroup, one wave each
 constexpr int kThreads = kWaves * kWave;     // 1024
-constexpr int64_t kLdsFloats = 40 * 1024;    // 160 KB of staged targets
+// staged targets: 160 KiB less 512 bytes for the kernels' static LDS (target
+// ids, offsets, the item index)
+constexpr int64_t kLdsFloats = (160 * 1024 - 512) / 4;
 
 static_assert(kGroups * kSubs == kWave, "lane layout");
 static_assert(kLookupItemMaxTargets == 16, "tile layout assumes at most 16 targets");
@@ -55,6 +61,9 @@ static_assert(kLookupItemMaxTargets == 16, "tile layout assumes at most 16 targe
 struct Sums {
   double so, sp, soo, spp, sop;
 };
+
+// Row stride (floats) of a staged tile of T targets.
+__host__ __device__ constexpr int tile_stride(int T) { return T; }
 
 template <int N>
 struct VecOf;
@@ -95,7 +104,7 @@ __device__ __forceinline__ void lds_read(const float *p, float (&v)[TPL]) {
 template <int K, int TPL, bool kPred>
 __device__ __forceinline__ void tile_pairs(const int32_t *__restrict__ tidx,
                                            const float *__restrict__ tw, const int m,
-                                           const float *vs, const int T, const int lgT,
+                                           const float *vs, const int T, const int S,
                                            float *const (&pred)[TPL], const float (&c)[TPL],
                                            Sums (&s)[TPL]) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -125,7 +134,7 @@ __device__ __forceinline__ void tile_pairs(const int32_t *__restrict__ tidx,
       float v[kChunk][TPL];
 #pragma unroll
       for (int i = i0; i < (i0 + kChunk < K ? i0 + kChunk : K); ++i)
-        lds_read<TPL>(base + (q[i] << lgT), v[i - i0]);
+        lds_read<TPL>(base + __umul24(q[i], S), v[i - i0]);  // q < 2^24: one full-rate multiply
 #pragma unroll
       for (int i = i0; i < (i0 + kChunk < K ? i0 + kChunk : K); ++i)
 #pragma unroll
@@ -133,7 +142,7 @@ __device__ __forceinline__ void tile_pairs(const int32_t *__restrict__ tidx,
       if (K > kChunk) __builtin_amdgcn_sched_barrier(0);
     }
     float ov[TPL];
-    lds_read<TPL>(base + (p << lgT), ov);
+    lds_read<TPL>(base + __umul24(p, S), ov);
 #pragma unroll
     for (int u = 0; u < TPL; ++u) {
       const double o = static_cast<double>(ov[u]);
@@ -168,10 +177,11 @@ __device__ __forceinline__ float pair_rho(int m, const Sums &s) {
 }
 
 // Stage targets tgt[0..Tn) over the window [off, off + n) into vs[e][t]
-// (row stride T, targets Tn..T-1 zero), relative to cs[t] = y_t[off]; zero
-// past a target's own length.  Ends with a barrier.
+// (row stride S = tile_stride(T), targets Tn..T-1 zero), relative to
+// cs[t] = y_t[off]; zero past a target's own length.  Ends with a barrier.
 __device__ __forceinline__ void stage_tile(const LookupArgs &a, const int *tgt, int Tn, int T,
                                            int lgT, int off, int n, float *vs, float *cs) {
+  const int S = tile_stride(T);
   if (static_cast<int>(threadIdx.x) < T) {
     const int t = threadIdx.x;
     float c = 0.0f;
@@ -196,7 +206,7 @@ __device__ __forceinline__ void stage_tile(const LookupArgs &a, const int *tgt, 
         v = y - cs[t];
       }
     }
-    vs[idx] = v;
+    vs[e * S + t] = v;
   }
   if (bad) atomicOr(a.status, 1);
   __syncthreads();
@@ -209,7 +219,8 @@ template <int K, int TPL>
 __device__ __forceinline__ void wave_library(const LookupArgs &a, const int32_t *tidx,
                                              const float *tw, int lib, int64_t Lx, int m,
                                              const float *vs, const float *cs, const int *tgt,
-                                             int Tn, int T, int lgT) {
+                                             int Tn, int T) {
+  const int S = tile_stride(T);
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (kSubs - 1);
   bool ok[TPL];
@@ -229,9 +240,9 @@ __device__ __forceinline__ void wave_library(const LookupArgs &a, const int32_t 
   // predictions are written only with one target per lane (tiles of at most
   // 4 targets), which keeps the wider instantiations free of their registers
   if (TPL == 1 && a.pred)
-    tile_pairs<K, TPL, TPL == 1>(tidx, tw, m, vs, T, lgT, pred, c, s);
+    tile_pairs<K, TPL, TPL == 1>(tidx, tw, m, vs, T, S, pred, c, s);
   else
-    tile_pairs<K, TPL, false>(tidx, tw, m, vs, T, lgT, pred, c, s);
+    tile_pairs<K, TPL, false>(tidx, tw, m, vs, T, S, pred, c, s);
   if (a.rho && lane < kSubs) {
 #pragma unroll
     for (int u = 0; u < TPL; ++u)
@@ -248,13 +259,26 @@ __global__ __launch_bounds__(kThreads) void k_lookup(LookupArgs a, int T, int ns
   float *vs = reinterpret_cast<float *>(lds4);
   __shared__ float cs[kLookupItemMaxTargets];
   __shared__ int tgt[kLookupItemMaxTargets];
-  const int t0 = static_cast<int>(blockIdx.x) * T;
-  const int sbase = slot0 + static_cast<int>(blockIdx.y) * kWaves;
   const int off = (a.E - 1) * a.tau + a.Tp;
-  const int Tn = a.ntgt - t0 < T ? a.ntgt - t0 : T;
+  // targets of the launch: the host's list, or the bucket grouped on the device
+  const bool dev = a.bucket_at != nullptr && a.tbl_off == nullptr;
+  const int ntgt = dev ? a.bucket_at[a.E + 1] - a.bucket_at[a.E] : a.ntgt;
+  const int32_t *tids = dev ? a.bucket_ids + a.bucket_at[a.E] : a.tgt_ids;
+  // Host grid: blockIdx.x = tile, blockIdx.y = library group.  Device-bucket
+  // grid (one dimension): workgroup i runs on XCD i % 8 (round-robin
+  // dispatch); the kTileCols tile columns of a library group all go to one
+  // XCD, so the workgroups an XCD runs together share two groups' tables in
+  // its L2.
+  int col = static_cast<int>(blockIdx.x), ncol = static_cast<int>(gridDim.x);
+  int grp = static_cast<int>(blockIdx.y);
+  if (dev) {
+    const int i = static_cast<int>(blockIdx.x), k = i / kXcds;
+    col = k % kTileCols;
+    ncol = kTileCols;
+    grp = kXcds * (k / kTileCols) + i % kXcds;
+  }
+  const int sbase = slot0 + grp * kWaves;
   const int lgT = 31 - __builtin_clz(T);
-  if (static_cast<int>(threadIdx.x) < Tn)
-    tgt[threadIdx.x] = a.tgt_ids ? a.tgt_ids[t0 + threadIdx.x] : t0 + static_cast<int>(threadIdx.x);
   int n_blk = 0;  // widest query range of the workgroup's libraries
   for (int w = 0; w < kWaves; ++w) {
     const int slot = sbase + w;
@@ -264,18 +288,27 @@ __global__ __launch_bounds__(kThreads) void k_lookup(LookupArgs a, int T, int ns
     const int mw = static_cast<int>(Lx) - off;
     n_blk = mw > n_blk ? mw : n_blk;
   }
-  if (n_blk - 1 < K) return;  // no table in this workgroup (uniform)
-  stage_tile(a, tgt, Tn, T, lgT, off, n_blk, vs, cs);
+  if (n_blk - 1 - 2 * a.excl < K) return;  // no table in this workgroup (uniform)
 
   const int wave = static_cast<int>(threadIdx.x) / kWave;
   const int slot = __builtin_amdgcn_readfirstlane(sbase + wave);
-  if (slot >= slot0 + nslots) return;
-  const int lib = a.lib_ids ? a.lib_ids[slot] : slot;
-  const int64_t Lx = a.Lx_dev ? a.Lx_dev[lib] : a.Lx_uni;
+  const bool in = slot < slot0 + nslots;
+  const int lib = in ? (a.lib_ids ? a.lib_ids[slot] : slot) : 0;
+  const int64_t Lx = in ? (a.Lx_dev ? a.Lx_dev[lib] : a.Lx_uni) : 0;
   const int m = static_cast<int>(Lx) - off;
-  if (m - 1 - 2 * a.excl < K) return;  // the table does not exist for this library
+  const bool on = in && m - 1 - 2 * a.excl >= K;  // the table exists for this library
   const int64_t tbl = static_cast<int64_t>(slot) * a.tbl_stride;
-  wave_library<K, TPL>(a, a.idx + tbl, a.w + tbl, lib, Lx, m, vs, cs, tgt, Tn, T, lgT);
+  // tiles blockIdx.x, blockIdx.x + gridDim.x, ... (one per workgroup when the
+  // host sized the grid to the target count)
+  for (int tile = col; tile * T < ntgt; tile += ncol) {
+    const int t0 = tile * T;
+    const int Tn = ntgt - t0 < T ? ntgt - t0 : T;
+    if (tile != col) __syncthreads();  // the previous tile is consumed
+    if (static_cast<int>(threadIdx.x) < Tn)
+      tgt[threadIdx.x] = tids ? tids[t0 + threadIdx.x] : t0 + static_cast<int>(threadIdx.x);
+    stage_tile(a, tgt, Tn, T, lgT, off, n_blk, vs, cs);
+    if (on) wave_library<K, TPL>(a, a.idx + tbl, a.w + tbl, lib, Lx, m, vs, cs, tgt, Tn, T);
+  }
 }
 
 // Work-list kernel for one E (K = E + 1): persistent (counter != nullptr:
@@ -327,11 +360,11 @@ __global__ __launch_bounds__(kThreads) void k_lookup_items(LookupArgs a,
       if (m - 1 - 2 * a.excl >= K) {
         const int64_t o = a.tbl_off[static_cast<int64_t>(lib) * (EDM_E_MAX + 1) + E];
         if (T >= 16)
-          wave_library<K, 4>(a, a.tbl_idx + o, a.tbl_w + o, lib, Lx, m, vs, cs, tgt, Tn, T, lgT);
+          wave_library<K, 4>(a, a.tbl_idx + o, a.tbl_w + o, lib, Lx, m, vs, cs, tgt, Tn, T);
         else if (T == 8)
-          wave_library<K, 2>(a, a.tbl_idx + o, a.tbl_w + o, lib, Lx, m, vs, cs, tgt, Tn, T, lgT);
+          wave_library<K, 2>(a, a.tbl_idx + o, a.tbl_w + o, lib, Lx, m, vs, cs, tgt, Tn, T);
         else
-          wave_library<K, 1>(a, a.tbl_idx + o, a.tbl_w + o, lib, Lx, m, vs, cs, tgt, Tn, T, lgT);
+          wave_library<K, 1>(a, a.tbl_idx + o, a.tbl_w + o, lib, Lx, m, vs, cs, tgt, Tn, T);
       }
     }
   }
@@ -361,9 +394,11 @@ constexpr auto make_table(std::index_sequence<I...>) {
 
 int lookup_tile_targets(int64_t m) {
   int T = kLookupItemMaxTargets;
-  while (T > 1 && static_cast<int64_t>(T) * m > kLdsFloats) T >>= 1;
+  while (T > 1 && static_cast<int64_t>(tile_stride(T)) * m > kLdsFloats) T >>= 1;
   return T;
 }
+
+int64_t lookup_tile_floats(int T, int64_t m) { return static_cast<int64_t>(tile_stride(T)) * m; }
 
 hipError_t launch_lookup(const LookupArgs &a, int nslots, int64_t m_max, hipStream_t st) {
   static const auto t4 = make_table<4>(std::make_index_sequence<EDM_K_MAX>{});
@@ -374,7 +409,7 @@ hipError_t launch_lookup(const LookupArgs &a, int nslots, int64_t m_max, hipStre
   int T = lookup_tile_targets(m_max);
   if (a.pred && T > 4) T = 4;                 // the prediction-writing form
   while (T > 1 && T / 2 >= a.ntgt) T >>= 1;  // no wider than the target count needs
-  const size_t shm = static_cast<size_t>(T) * static_cast<size_t>(m_max) * sizeof(float);
+  const size_t shm = static_cast<size_t>(lookup_tile_floats(T, m_max)) * sizeof(float);
   const unsigned gx = static_cast<unsigned>((a.ntgt + T - 1) / T);
   const auto &table = T >= 16 ? t4 : (T == 8 ? t2 : t1);
   TimedLaunch timed(EDM_KF_LOOKUP, st);
@@ -383,6 +418,34 @@ hipError_t launch_lookup(const LookupArgs &a, int nslots, int64_t m_max, hipStre
     const int ns = nslots - s0 < kMaxY ? nslots - s0 : kMaxY;
     const unsigned gy = static_cast<unsigned>((ns + kWaves - 1) / kWaves);
     hipError_t e = table[a.k - 1](a, dim3(gx, gy), shm, T, ns, s0, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_lookup_bucket(const LookupArgs &a, int nslots, int64_t m_max, int64_t n_tgt_max,
+                                hipStream_t st) {
+  static const auto t4 = make_table<4>(std::make_index_sequence<EDM_K_MAX>{});
+  static const auto t2 = make_table<2>(std::make_index_sequence<EDM_K_MAX>{});
+  static const auto t1 = make_table<1>(std::make_index_sequence<EDM_K_MAX>{});
+  if (nslots <= 0 || n_tgt_max <= 0 || m_max <= 0) return hipSuccess;
+  if (a.k < 1 || a.k > EDM_K_MAX || m_max > kLdsFloats || !a.bucket_at || !a.bucket_ids || a.tbl_off ||
+      a.pred)
+    return hipErrorInvalidValue;
+  int T = lookup_tile_targets(m_max);
+  while (T > 1 && T / 2 >= n_tgt_max) T >>= 1;
+  const size_t shm = static_cast<size_t>(lookup_tile_floats(T, m_max)) * sizeof(float);
+  // kTileCols tile columns per library group, each workgroup walking its
+  // column's tiles; library groups padded to a multiple of the XCD count
+  // (the kernel maps workgroups to groups XCD by XCD)
+  const auto &table = T >= 16 ? t4 : (T == 8 ? t2 : t1);
+  TimedLaunch timed(EDM_KF_LOOKUP, st);
+  constexpr int kMaxSlots = 65536 * kWaves;
+  for (int s0 = 0; s0 < nslots; s0 += kMaxSlots) {
+    const int ns = nslots - s0 < kMaxSlots ? nslots - s0 : kMaxSlots;
+    const int64_t groups = (ns + kWaves - 1) / kWaves;
+    const int64_t padded = (groups + kXcds - 1) / kXcds * kXcds;
+    hipError_t e = table[a.k - 1](a, dim3(static_cast<unsigned>(padded * kTileCols), 1), shm, T, ns, s0, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

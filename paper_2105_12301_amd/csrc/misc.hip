@@ -67,6 +67,71 @@ __global__ void k_candidates(const float *__restrict__ logits, int64_t N, int32_
   cand[s] = m ? m : all;
 }
 
+// One workgroup of 1024 threads: histogram of E in LDS, exclusive scan,
+// then a stable scatter in chunks of 1024 targets (per bin, each wave counts
+// its lanes with a ballot; waves are ranked in order), so a bucket lists its
+// targets in ascending order on every run.
+constexpr int kGroupThreads = 1024;
+constexpr int kBins = EDM_E_MAX + 1;
+__global__ __launch_bounds__(kGroupThreads) void k_group_by_E(const int32_t *__restrict__ E, int64_t N,
+                                                              int32_t E_max, int32_t *__restrict__ at,
+                                                              int32_t *__restrict__ ids) {
+  constexpr int kW = kGroupThreads / kWave;
+  __shared__ int cnt[kBins];
+  __shared__ int base[kBins];
+  __shared__ int wc[kW][kBins];
+  const int t = static_cast<int>(threadIdx.x);
+  const int lane = t & (kWave - 1), wv = t / kWave;
+  if (t < kBins) cnt[t] = 0;
+  __syncthreads();
+  auto bin = [&](int64_t j) {
+    const int e = E[j];
+    return (e >= 1 && e <= E_max) ? e : 0;
+  };
+  for (int64_t j = t; j < N; j += kGroupThreads) atomicAdd(&cnt[bin(j)], 1);
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int b = 0; b < kBins; ++b) {
+      base[b] = acc;
+      at[b] = acc;
+      acc += cnt[b];
+    }
+    at[kBins] = acc;
+  }
+  __syncthreads();
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  for (int64_t c0 = 0; c0 < N; c0 += kGroupThreads) {
+    const int64_t j = c0 + t;
+    const int b = j < N ? bin(j) : -1;
+    int rank = 0;
+    for (int q = 0; q < kBins; ++q) {
+      const uint64_t m = __builtin_amdgcn_ballot_w64(b == q);
+      if (b == q) rank = __builtin_popcountll(m & below);
+      if (lane == 0) wc[wv][q] = __builtin_popcountll(m);
+    }
+    __syncthreads();
+    if (b >= 0) {
+      int off = base[b];
+      for (int w = 0; w < wv; ++w) off += wc[w][b];
+      ids[off + rank] = static_cast<int32_t>(j);
+    }
+    __syncthreads();
+    if (t < kBins) {
+      int add = 0;
+      for (int w = 0; w < kW; ++w) add += wc[w][t];
+      base[t] += add;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_fill_i64(int64_t *__restrict__ p, int64_t n, int64_t v) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
 __global__ void k_fill(float *__restrict__ p, int64_t n, float v) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -109,6 +174,14 @@ hipError_t launch_sweep_finalize(const Mom *mom, int32_t mom_blocks, const int64
   return hipGetLastError();
 }
 
+hipError_t launch_group_by_E(const int32_t *E, int64_t N, int32_t E_max, int32_t *at, int32_t *ids,
+                             hipStream_t st) {
+  if (N < 0 || N > INT32_MAX || E_max < 1 || E_max > EDM_E_MAX) return hipErrorInvalidValue;
+  TimedLaunch timed(EDM_KF_GROUP, st);
+  hipLaunchKernelGGL(k_group_by_E, dim3(1), dim3(kGroupThreads), 0, st, E, N, E_max, at, ids);
+  return hipGetLastError();
+}
+
 hipError_t launch_candidates(const float *logits, int64_t N, int32_t E_max, int32_t m_top,
                              float min_conf, uint32_t *cand, hipStream_t st) {
   if (N <= 0) return hipSuccess;
@@ -122,6 +195,13 @@ hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   TimedLaunch timed(EDM_KF_OTHER, st);
   hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  TimedLaunch timed(EDM_KF_OTHER, st);
+  hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
 

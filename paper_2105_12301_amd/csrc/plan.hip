@@ -256,7 +256,7 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
         // whose tile fits the lookup kernel's LDS
         int64_t T = edm::lookup_tile_targets(m);
         while (T > tn.lookup_targets) T >>= 1;
-        B.lds_floats[E] = std::max(B.lds_floats[E], T * m);
+        B.lds_floats[E] = std::max(B.lds_floats[E], edm::lookup_tile_floats(static_cast<int>(T), m));
         const int32_t at = static_cast<int32_t>(item_libs.size());
         item_libs.insert(item_libs.end(), grp.begin(), grp.end());
         for (int64_t f = 0; f < cnt; f += T)

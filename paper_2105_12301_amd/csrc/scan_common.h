@@ -124,10 +124,13 @@ __device__ __forceinline__ Mom finish_list(const KnnArgs &a, int row, int p, int
       }
     } else {
       if (a.keepE[E]) {  // sweep mode: keep the sorted list for a later cross map
-        int32_t *kp = a.keepE[E] + static_cast<int64_t>(row) * a.keep_strideE[E] +
-                      static_cast<int64_t>(p) * K;
+        const int64_t ko = static_cast<int64_t>(row) * a.keep_strideE[E] + static_cast<int64_t>(p) * K;
 #pragma unroll
-        for (int i = 0; i < K; ++i) kp[i] = qi[OFF + i];
+        for (int i = 0; i < K; ++i) a.keepE[E][ko + i] = qi[OFF + i];
+        if (a.keepWE[E]) {
+#pragma unroll
+          for (int i = 0; i < K; ++i) a.keepWE[E][ko + i] = static_cast<float>(D[i] * inv);
+        }
       }
       const int o_off = (E - 1) + Tp;
       double yh = 0.0;

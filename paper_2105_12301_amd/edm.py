@@ -320,14 +320,17 @@ def edm_ccm(X, E_tgt, Y=None, Lx=None, Ly=None, tau: int = 1, Tp: int = 0, rho=N
 
 
 def edm_sweep_ccm(X, lengths=None, E_max: int = E_MAX, tau: int = 1, rho=None,
-                  ctx: Context | None = None):
+                  ctx: Context | None = None, rho_sweep=None, E_opt=None):
     """E sweep (Tp = 1) then all-to-all CCM of the same series at the targets'
-    E* (Tp = 0).  Returns (rho_sweep [N][E_max], E_opt [N], rho [N][N])."""
+    E* (Tp = 0).  Returns (rho_sweep [N][E_max], E_opt [N], rho [N][N]);
+    rho_sweep, E_opt and rho may be given (preallocated outputs)."""
     ctx = ctx or default_context(X.device)
     N, ldx = X.shape
     L = _host_i64(np.full(N, ldx) if lengths is None else lengths, N, "lengths")
-    rho_s = torch.empty((N, E_max), dtype=torch.float32, device=X.device)
-    E_opt = torch.empty((N,), dtype=torch.int32, device=X.device)
+    rho_s = rho_sweep if rho_sweep is not None else torch.empty((N, E_max), dtype=torch.float32,
+                                                                device=X.device)
+    if E_opt is None:
+        E_opt = torch.empty((N,), dtype=torch.int32, device=X.device)
     if rho is None:
         rho = torch.empty((N, N), dtype=torch.float32, device=X.device)
     _check(load_library().edm_sweep_ccm(
