@@ -383,13 +383,18 @@ int edm_lookup(edm_ctx *ctx, const int32_t *idx, const float *w, int64_t nq, int
   if (rc != EDM_OK) return set_err(ctx, rc, msg);
   EDM_RC(check_ctx(ctx));
   if (N == 0) return EDM_OK;
+  const int64_t Lx = nq + static_cast<int64_t>(E - 1) * tau + Tp;
+  EDM_RC(ws_reserve(ctx, sizeof(float) * static_cast<size_t>(N)));
+  float *cm = reinterpret_cast<float *>(ctx->ws);
+  EDM_HIP(ctx, edm::launch_target_means(Y, ldy, nullptr, Lx, N, cm, ctx->stream));
   edm::LookupArgs b{};
   b.idx = idx;
   b.w = w;
   b.tbl_stride = 0;
   b.lib_ids = nullptr;
   b.Lx_dev = nullptr;
-  b.Lx_uni = nq + static_cast<int64_t>(E - 1) * tau + Tp;
+  b.Lx_uni = Lx;
+  b.cmean = cm;
   b.E = E;
   b.tau = tau;
   b.Tp = Tp;
@@ -515,6 +520,7 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
   const size_t off_L = plan.take(sizeof(int64_t) * N);
   const size_t off_ids = plan.take(sizeof(int32_t) * N);
   const size_t off_at = plan.take(sizeof(int32_t) * (EDM_E_MAX + 2));
+  const size_t off_cm = plan.take(sizeof(float) * N);
   const size_t off_mom = plan.take(edm::kMomBytes * static_cast<size_t>(N) * E_max * mom_blocks);
   size_t off_gmu = 0, off_gnrm = 0;
   if (gram) {
@@ -542,6 +548,7 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
   int64_t *L_dev = reinterpret_cast<int64_t *>(ctx->ws + off_L);
   int32_t *ids_dev = reinterpret_cast<int32_t *>(ctx->ws + off_ids);
   int32_t *at_dev = reinterpret_cast<int32_t *>(ctx->ws + off_at);
+  float *cm_dev = reinterpret_cast<float *>(ctx->ws + off_cm);
   edm::Mom *mom = reinterpret_cast<edm::Mom *>(ctx->ws + off_mom);
   // Equal lengths are written on the device: the call then makes no host
   // transfer and no synchronisation at all (it can be captured in a graph).
@@ -579,6 +586,7 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
   // Targets by their selected E (Section 3.4), grouped on the device: every
   // E is launched, and its kernels exit at once when its bucket is empty.
   EDM_HIP(ctx, edm::launch_group_by_E(E_opt, N, E_max, at_dev, ids_dev, ctx->stream));
+  EDM_HIP(ctx, edm::launch_target_means(X, ldx, L_dev, 0, N, cm_dev, ctx->stream));
   EDM_HIP(ctx, edm::launch_fill(rho, N * N, __builtin_nanf(""), ctx->stream));
 
   for (int e = 1; e <= E_max; ++e) {
@@ -612,6 +620,7 @@ int edm_sweep_ccm(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int
     b.Tp = 0;
     b.k = e + 1;
     b.Y = X;
+    b.cmean = cm_dev;
     b.ldy = ldx;
     b.Ly_dev = L_dev;
     b.bucket_ids = ids_dev;
@@ -653,6 +662,7 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
   const size_t off_Ly = plan.take(sizeof(int64_t) * Nt);
   const size_t off_ids = plan.take(sizeof(int32_t) * Nt);
   const size_t small_bytes = plan.bytes;
+  const size_t off_cm = plan.take(sizeof(float) * Nt);
   const size_t off_tbl = plan.take(0);
   // Table bytes of one library: the largest E in use (plain form, one E at a
   // time) or every E in use together (chosen form, one scan per E group).
@@ -701,9 +711,11 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
   EDM_RC(upload(ctx, blob.data(), small_bytes, ctx->ws));
   const int64_t *Lx_dev = reinterpret_cast<const int64_t *>(ctx->ws + off_Lx);
   const int64_t *Ly_dev = reinterpret_cast<const int64_t *>(ctx->ws + off_Ly);
+  float *cm_dev = reinterpret_cast<float *>(ctx->ws + off_cm);
   const int32_t *ids_dev = reinterpret_cast<const int32_t *>(ctx->ws + off_ids);
 
   EDM_HIP(ctx, edm::launch_fill(rho, Nl * Nt, __builtin_nanf(""), ctx->stream));
+  EDM_HIP(ctx, edm::launch_target_means(Y, ldy, Ly_dev, 0, Nt, cm_dev, ctx->stream));
 
   if (batched) {
     // Chosen form: per library batch, one scan per E group writes the tables
@@ -755,6 +767,7 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
         b.Tp = Tp;
         b.k = e + 1;
         b.Y = Y;
+        b.cmean = cm_dev;
         b.ldy = ldy;
         b.Ly_dev = Ly_dev;
         b.tgt_ids = ids_dev + bucket_at[e];
@@ -807,6 +820,7 @@ int edm_ccm(edm_ctx *ctx, const float *X, const int64_t *Lx, int64_t Nl, int64_t
       b.k = k;
       b.excl = ctx->excl;
       b.Y = Y;
+      b.cmean = cm_dev;
       b.ldy = ldy;
       b.Ly_dev = Ly_dev;
       b.tgt_ids = ids_dev + bucket_at[e];
@@ -857,6 +871,7 @@ int edm_ccm_subsample(edm_ctx *ctx, const float *x, int64_t L, const float *Y, i
   const size_t off_off = plan.take(sizeof(int64_t) * static_cast<size_t>(S + 1));
   const size_t small = plan.bytes;
   const size_t off_idx = plan.take(idx ? 0 : sizeof(int32_t) * static_cast<size_t>(stride) * S);
+  const size_t off_cm = plan.take(sizeof(float) * static_cast<size_t>(Nt));
   const size_t off_w = plan.take(sizeof(float) * static_cast<size_t>(stride) * S);
   if (plan.bytes > workspace_limit()) return set_err(ctx, EDM_E_NOMEM, "subsample tables exceed EDM_WORKSPACE_LIMIT");
   EDM_RC(ws_reserve(ctx, plan.bytes));
@@ -881,11 +896,14 @@ int edm_ccm_subsample(edm_ctx *ctx, const float *x, int64_t L, const float *Y, i
                                        reinterpret_cast<const int64_t *>(ctx->ws + off_off),
                                        static_cast<int>(S), ctx->stream));
   if (Nt == 0) return EDM_OK;
+  float *cm = reinterpret_cast<float *>(ctx->ws + off_cm);
+  EDM_HIP(ctx, edm::launch_target_means(Y, ldy, nullptr, L, Nt, cm, ctx->stream));
   edm::LookupArgs b{};
   b.idx = a.idx;
   b.w = a.w;
   b.tbl_stride = stride;
   b.Lx_uni = L;
+  b.cmean = cm;
   b.E = E;
   b.tau = tau;
   b.Tp = Tp;

@@ -179,6 +179,7 @@ struct LookupArgs {
   int32_t E, tau, Tp, k;
   int32_t excl;              // exclusion radius of the tables (a table exists iff m-1-2*excl >= k)
   const float *Y;            // targets, row j at Y + j*ldy
+  const float *cmean;        // centring constant of every target (launch_target_means)
   int64_t ldy;
   const int64_t *Ly_dev;     // target lengths (device) or nullptr -> every target long enough
   const int32_t *tgt_ids;    // bucket position -> target id (device) or nullptr -> identity
@@ -210,6 +211,11 @@ hipError_t launch_lookup_items(const LookupArgs &a, int E, const LookupItem *ite
                                hipStream_t st);
 
 hipError_t launch_lookup(const LookupArgs &a, int nslots, int64_t m_max, hipStream_t st);
+
+// Centring constants of targets Y[N][ldy] for the lookups: the float32 of each
+// target's float64 mean over [0, Ly_dev[t]) (or [0, L_uni)).
+hipError_t launch_target_means(const float *Y, int64_t ldy, const int64_t *Ly_dev, int64_t L_uni,
+                               int64_t N, float *cmean, hipStream_t st);
 
 // Targets per staged lookup tile for a window of m samples: the largest of
 // 16, 8, 4, 2, 1 whose tile fits the lookup kernels' 160 KB of LDS.

@@ -4,7 +4,9 @@
 // Data layout.  A workgroup stages a tile of T targets (T in 1, 2, 4, 8, 16,
 // as many as fit 160 KB of LDS for the window) over the window that its
 // libraries' tables can touch, interleaved: vs[e][t] = y_t[off + e] - c_t with
-// c_t = y_t[off], off = (E-1)*tau + Tp, rows S = tile_stride(T) floats apart.
+// c_t the target's mean (k_target_means, one value per target and call, the
+// same for every kernel), off = (E-1)*tau + Tp, rows S = tile_stride(T) floats
+// apart.
 // One neighbour index q then addresses the T targets' samples as one
 // contiguous LDS segment, so a wave reads them with one 128-, 64- or 32-bit
 // access per lane instead of T scattered 32-bit gathers.  (Rows padded to
@@ -18,14 +20,16 @@
 // row (K indices and weights, shared by the 4 lanes of the group), gathers
 // vs[q_i][targets] for i = 0..K-1 and accumulates the prediction
 // yhat = sum_i w_i (y(t(q_i)+Tp) - c) with one float32 fused multiply-add per
-// neighbour in index order, and float64 sums of the observation o = vs[p] and
-// yhat: so, sp, soo, spp, sop.  The prediction is taken relative to c (the
-// weights sum to one), which keeps float32 cancellation proportional to the
-// target's spread.
+// neighbour in index order, and the sums of the observation o = vs[p] and
+// yhat: so, sp, soo, spp, sop, accumulated in float32 over runs of kRun
+// queries and added to float64 totals after each run.  Both sides are taken
+// relative to the target's mean (the weights sum to one, so the prediction's
+// mean is near it too): the float32 runs then round values of the target's
+// spread, not of its offset, and the correlation keeps errors of order 1e-8.
 //
-// Every pair's arithmetic is fixed: per query group the float64 sums run over
-// p in increasing order, then the 16 group sums meet in a butterfly over the
-// lane bits of g (masks 4, 8, 16, 32).  It does not depend on T, on which
+// Every pair's arithmetic is fixed: per query group the runs and the float64
+// sums go over p in increasing order, then the 16 group sums meet in a
+// butterfly over the lane bits of g (masks 4, 8, 16, 32).  It does not depend on T, on which
 // kernel ran the pair or on how many libraries or targets shared a
 // workgroup, so every kernel here and every form of the library give
 // bit-identical rho.
@@ -46,6 +50,7 @@ namespace edm {
 namespace {
 
 constexpr int kGroups = 16;                  // query groups per wave
+constexpr int kRun = 8;                      // queries per float32 run of the skill sums
 constexpr int kXcds = 8;                     // accelerator dies (separate L2 caches) of the chip
 constexpr int kTileCols = 16;                // tile columns per library group (device buckets)
 constexpr int kSubs = 4;                     // lanes per query group
@@ -115,47 +120,61 @@ __device__ __forceinline__ void tile_pairs(const int32_t *__restrict__ tidx,
   const float *base = vs + col;
 #pragma unroll
   for (int u = 0; u < TPL; ++u) s[u] = Sums{0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int p = g; p < m; p += kGroups) {
-    const int64_t row = static_cast<int64_t>(p) * K;
-    int q[K];
-    float w[K];
+  for (int p0 = g; p0 < m; p0 += kGroups * kRun) {
+    const int pe = m < p0 + kGroups * kRun ? m : p0 + kGroups * kRun;
+    float f[TPL][5];
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      q[i] = tidx[row + i];
-      w[i] = tw[row + i];
+    for (int u = 0; u < TPL; ++u)
+#pragma unroll
+      for (int j = 0; j < 5; ++j) f[u][j] = 0.0f;
+    for (int p = p0; p < pe; p += kGroups) {
+      const int64_t row = static_cast<int64_t>(p) * K;
+      int q[K];
+      float w[K];
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        q[i] = tidx[row + i];
+        w[i] = tw[row + i];
+      }
+      float yh[TPL];
+#pragma unroll
+      for (int u = 0; u < TPL; ++u) yh[u] = 0.0f;
+      // gathers in chunks of kChunk neighbours (bounds the registers in flight)
+      constexpr int kChunk = TPL == 4 ? 4 : (TPL == 2 ? 8 : 16);
+#pragma unroll
+      for (int i0 = 0; i0 < K; i0 += kChunk) {
+        float v[kChunk][TPL];
+#pragma unroll
+        for (int i = i0; i < (i0 + kChunk < K ? i0 + kChunk : K); ++i)
+          lds_read<TPL>(base + __umul24(q[i], S), v[i - i0]);  // q < 2^24: one full-rate multiply
+#pragma unroll
+        for (int i = i0; i < (i0 + kChunk < K ? i0 + kChunk : K); ++i)
+#pragma unroll
+          for (int u = 0; u < TPL; ++u) yh[u] = fmaf(w[i], v[i - i0][u], yh[u]);
+        if (K > kChunk) __builtin_amdgcn_sched_barrier(0);
+      }
+      float ov[TPL];
+      lds_read<TPL>(base + __umul24(p, S), ov);
+#pragma unroll
+      for (int u = 0; u < TPL; ++u) {
+        // explicit fused forms: the same operations in every instantiation
+        f[u][0] += ov[u];
+        f[u][1] += yh[u];
+        f[u][2] = fmaf(ov[u], ov[u], f[u][2]);
+        f[u][3] = fmaf(yh[u], yh[u], f[u][3]);
+        f[u][4] = fmaf(ov[u], yh[u], f[u][4]);
+        if constexpr (kPred) {
+          if (pred[u]) pred[u][p] = yh[u] + c[u];
+        }
+      }
     }
-    float yh[TPL];
-#pragma unroll
-    for (int u = 0; u < TPL; ++u) yh[u] = 0.0f;
-    // gathers in chunks of kChunk neighbours (bounds the registers in flight)
-    constexpr int kChunk = TPL == 4 ? 4 : (TPL == 2 ? 8 : 16);
-#pragma unroll
-    for (int i0 = 0; i0 < K; i0 += kChunk) {
-      float v[kChunk][TPL];
-#pragma unroll
-      for (int i = i0; i < (i0 + kChunk < K ? i0 + kChunk : K); ++i)
-        lds_read<TPL>(base + __umul24(q[i], S), v[i - i0]);  // q < 2^24: one full-rate multiply
-#pragma unroll
-      for (int i = i0; i < (i0 + kChunk < K ? i0 + kChunk : K); ++i)
-#pragma unroll
-        for (int u = 0; u < TPL; ++u) yh[u] = fmaf(w[i], v[i - i0][u], yh[u]);
-      if (K > kChunk) __builtin_amdgcn_sched_barrier(0);
-    }
-    float ov[TPL];
-    lds_read<TPL>(base + __umul24(p, S), ov);
 #pragma unroll
     for (int u = 0; u < TPL; ++u) {
-      const double o = static_cast<double>(ov[u]);
-      const double ph = static_cast<double>(yh[u]);
-      // explicit fused forms: the same operations in every instantiation
-      s[u].so += o;
-      s[u].sp += ph;
-      s[u].soo = fma(o, o, s[u].soo);
-      s[u].spp = fma(ph, ph, s[u].spp);
-      s[u].sop = fma(o, ph, s[u].sop);
-      if constexpr (kPred) {
-        if (pred[u]) pred[u][p] = yh[u] + c[u];
-      }
+      s[u].so += static_cast<double>(f[u][0]);
+      s[u].sp += static_cast<double>(f[u][1]);
+      s[u].soo += static_cast<double>(f[u][2]);
+      s[u].spp += static_cast<double>(f[u][3]);
+      s[u].sop += static_cast<double>(f[u][4]);
     }
   }
 #pragma unroll
@@ -178,18 +197,14 @@ __device__ __forceinline__ float pair_rho(int m, const Sums &s) {
 
 // Stage targets tgt[0..Tn) over the window [off, off + n) into vs[e][t]
 // (row stride S = tile_stride(T), targets Tn..T-1 zero), relative to
-// cs[t] = y_t[off]; zero past a target's own length.  Ends with a barrier.
+// cs[t] = a.cmean[target]; zero past a target's own length.  Ends with a
+// barrier.
 __device__ __forceinline__ void stage_tile(const LookupArgs &a, const int *tgt, int Tn, int T,
                                            int lgT, int off, int n, float *vs, float *cs) {
   const int S = tile_stride(T);
   if (static_cast<int>(threadIdx.x) < T) {
     const int t = threadIdx.x;
-    float c = 0.0f;
-    if (t < Tn) {
-      const int64_t Ly = a.Ly_dev ? a.Ly_dev[tgt[t]] : a.ldy;
-      if (Ly > off) c = a.Y[static_cast<int64_t>(tgt[t]) * a.ldy + off];
-    }
-    cs[t] = c;
+    cs[t] = t < Tn ? a.cmean[tgt[t]] : 0.0f;
   }
   __syncthreads();
   bool bad = false;
@@ -370,6 +385,25 @@ __global__ __launch_bounds__(kThreads) void k_lookup_items(LookupArgs a,
   }
 }
 
+// Centring constant of every target: float32 of the float64 mean over
+// [0, Ly) (Ly_dev, or L_uni for all), one wave per target summing in a fixed
+// order (lane-strided, then a butterfly), so every kernel and call that
+// stages the target subtracts the same value.
+__global__ __launch_bounds__(256) void k_target_means(const float *__restrict__ Y, int64_t ldy,
+                                                      const int64_t *__restrict__ Ly_dev, int64_t L_uni,
+                                                      int64_t N, float *__restrict__ cmean) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * (256 / kWave) + threadIdx.x / kWave;
+  if (t >= N) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t L = Ly_dev ? Ly_dev[t] : L_uni;
+  const float *__restrict__ y = Y + t * ldy;
+  double sum = 0.0;
+  for (int64_t i = lane; i < L; i += kWave) sum += static_cast<double>(y[i]);
+#pragma unroll
+  for (int msk = kWave / 2; msk > 0; msk >>= 1) sum += __shfl_xor(sum, msk);
+  if (lane == 0) cmean[t] = L > 0 ? static_cast<float>(sum / static_cast<double>(L)) : 0.0f;
+}
+
 using LaunchFn = hipError_t (*)(const LookupArgs &, dim3, size_t, int, int, int, hipStream_t);
 
 template <int K, int TPL>
@@ -391,6 +425,17 @@ constexpr auto make_table(std::index_sequence<I...>) {
 }
 
 }  // namespace
+
+hipError_t launch_target_means(const float *Y, int64_t ldy, const int64_t *Ly_dev, int64_t L_uni,
+                               int64_t N, float *cmean, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  TimedLaunch timed(EDM_KF_LOOKUP, st);
+  const int64_t blocks = (N + 3) / 4;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_target_means, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, Y, ldy, Ly_dev,
+                     L_uni, N, cmean);
+  return hipGetLastError();
+}
 
 int lookup_tile_targets(int64_t m) {
   int T = kLookupItemMaxTargets;

@@ -86,6 +86,7 @@ struct edm_plan {
   int64_t Lg_max = 0, gram_ld = 0;
   float *gram_mu = nullptr;
   uint32_t *gram_nrm = nullptr;
+  float *cmean = nullptr;  // targets' centring constants (computed in every run)
   std::vector<Batch> batches;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -297,6 +298,7 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
   const size_t oTidx = lay.take(sizeof(int32_t) * max_batch_elems);
   const size_t oTw = lay.take(sizeof(float) * max_batch_elems);
   // filter prep of every library: centring constants and packed norms
+  const size_t oCm = lay.take(sizeof(float) * Nt);
   const size_t oGmu = P->filtered ? lay.take(sizeof(float) * Nl) : 0;
   const size_t oGnrm =
       P->filtered ? lay.take(sizeof(uint32_t) * static_cast<size_t>(Nl) * edm::kGramNE * P->gram_ld) : 0;
@@ -318,6 +320,7 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
   P->item_libs = reinterpret_cast<int32_t *>(P->dev + oIl);
   P->tbl_idx = reinterpret_cast<int32_t *>(P->dev + oTidx);
   P->tbl_w = reinterpret_cast<float *>(P->dev + oTw);
+  P->cmean = reinterpret_cast<float *>(P->dev + oCm);
   if (P->filtered) {
     P->gram_mu = reinterpret_cast<float *>(P->dev + oGmu);
     P->gram_nrm = reinterpret_cast<uint32_t *>(P->dev + oGnrm);
@@ -352,6 +355,7 @@ int enqueue_plan(edm_ctx *ctx, edm_plan *P, const float *X, const float *Y, floa
   EDM_HIP(ctx, edm::launch_fill(rho, P->Nl * P->Nt, __builtin_nanf(""), st));
   // counters start at 0: an all-zero float fill writes zero bits
   EDM_HIP(ctx, edm::launch_fill(reinterpret_cast<float *>(P->counters), P->n_counters, 0.0f, st));
+  EDM_HIP(ctx, edm::launch_target_means(Y, P->ldy, P->Ly_dev, 0, P->Nt, P->cmean, st));
   edm::KnnArgs a{};
   a.X = X;
   a.ldx = P->ldx;
@@ -391,6 +395,7 @@ int enqueue_plan(edm_ctx *ctx, edm_plan *P, const float *X, const float *Y, floa
     b.tau = 1;
     b.Tp = P->Tp;
     b.Y = Y;
+    b.cmean = P->cmean;
     b.ldy = P->ldy;
     b.Ly_dev = P->Ly_dev;
     b.rho = rho;
