@@ -278,7 +278,12 @@ def family_work(fam, form, N, L, E_max, E_star):
     return None, None, None
 
 
-def kernel_table(fams, steps, form, N, L, E_max, E_star):
+def kernel_table(fams, steps, form, N, L, E_max, E_star, ceil=None):
+    """Per kernel family: time per step, launches, algorithmic work and its
+    fraction of the published peak (and of the measured ceiling, if given)."""
+    measured = {} if not ceil else {"hbm": ceil["hbm_copy_GBps"] * 1e9,
+                                    "mfma": ceil["mfma_bf16_TFLOPs"] * 1e12,
+                                    "alu": ceil["valu_fp32_Tops"] * 1e12}
     out = {}
     for fam, (ms, launches) in fams.items():
         if launches == 0:
@@ -291,6 +296,8 @@ def kernel_table(fams, steps, form, N, L, E_max, E_star):
             ach = work / (ms_step / 1e3)
             row.update({"bound": bound, "work_per_step": work, "achieved": ach / scale,
                         "peak": peak / scale, "unit": unit, "frac": ach / peak, "kernel": desc})
+            if bound in measured:
+                row["frac_of_measured_ceiling"] = ach / measured[bound]
         out[fam] = row
     return out
 
@@ -308,7 +315,8 @@ def roofline_of(kt, steps):
             "peak": r["peak"], "unit": r["unit"], "frac": r["frac"], "traffic": traffic,
             "traffic_source": None if tr is None else tr["source"],
             "avg_launch_ms": r["ms_per_step"] / r["launches_per_step"],
-            "work_per_launch": r["work_per_step"] / r["launches_per_step"]}
+            "work_per_launch": r["work_per_step"] / r["launches_per_step"],
+            "frac_of_measured_ceiling": r.get("frac_of_measured_ceiling")}
 
 
 def parity_subset(group, N, seed=4):
@@ -345,11 +353,12 @@ def bench_main(args, torch, edm, synth, wl, name):
              "all": [edm.EDM_FORM_PLAIN, edm.EDM_FORM_BATCHED, edm.EDM_FORM_CHOSEN],
              "chosen": [edm.EDM_FORM_CHOSEN]}[args.form]
     names = {edm.EDM_FORM_PLAIN: "plain", edm.EDM_FORM_BATCHED: "batched", edm.EDM_FORM_CHOSEN: "chosen"}
+    ceil = ctx.ceilings()  # this library's own copy, MFMA and VALU kernels
     res = {}
     for f in forms:
         res[names[f]] = run_form(torch, edm, ctx, Xd, rho, E_max, args.steps, args.warmup, f, True)
     r = res["chosen"]
-    kt = kernel_table(r["families"], args.steps, "chosen", N, L, E_max, r["Es"])
+    kt = kernel_table(r["families"], args.steps, "chosen", N, L, E_max, r["Es"], ceil)
     out = {
         "metric": "CCM pairs/sec at rho err <=1e-5 vs FP64 oracle; chosen vs plain form, 1 GPU",
         "value": pairs / (r["ms_per_step"] / 1e3),
@@ -368,6 +377,7 @@ def bench_main(args, torch, edm, synth, wl, name):
         "E_star_hist": np.bincount(r["Es"], minlength=E_max + 1)[1:].tolist(),
         "kernels": kt,
         "roofline": roofline_of(kt, args.steps),
+        "measured_ceilings": ceil,
     }
     for fname in res:
         if fname == "chosen":
@@ -376,7 +386,7 @@ def bench_main(args, torch, edm, synth, wl, name):
         same = (np.array_equal(p["rs"].view(np.int32), r["rs"].view(np.int32))
                 and np.array_equal(p["Es"], r["Es"])
                 and np.array_equal(p["rho"].view(np.int32), r["rho"].view(np.int32)))
-        kp = kernel_table(p["families"], args.steps, fname, N, L, E_max, p["Es"])
+        kp = kernel_table(p["families"], args.steps, fname, N, L, E_max, p["Es"], ceil)
         out[fname] = {"value": pairs / (p["ms_per_step"] / 1e3), "ms_per_step": p["ms_per_step"],
                       "kernels": kp, "chosen_speedup": p["ms_per_step"] / r["ms_per_step"],
                       "chosen_bit_identical": bool(same)}

@@ -162,6 +162,16 @@ int edm_ctx_set_timing(edm_ctx *ctx, int on);
  * (host arrays; either may be NULL) and clear the records. */
 int edm_ctx_timing(edm_ctx *ctx, double *ms, int64_t *launches);
 
+/* Empirical ceilings of the device, measured with the library's own kernels
+ * on the context's stream (Section 4.4 builds its rooflines from measured
+ * ceilings): HBM streaming bandwidth of a vectorised copy of 2 GiB (bytes
+ * read + written per second, GB/s), BF16 matrix-core throughput of
+ * independent v_mfma_f32_32x32x16_bf16 chains (TFLOP/s, 2 flops per
+ * multiply-add) and float32 vector throughput of independent non-fused
+ * additions (T ops/s).  Uses 4 GiB of workspace; synchronises the stream.
+ * Outputs are host doubles. */
+int edm_ceilings(edm_ctx *ctx, double *hbm_gbps, double *mfma_bf16_tflops, double *valu_fp32_tops);
+
 /* Time-delay embedding, Section 2.1 step 1.
  * x   : float32 [L]
  * out : float32 [n][E], n = L - (E-1)*tau, out[p][j] = x[p + j*tau]. */
@@ -268,8 +278,10 @@ int edm_simplex_sweep_noalloc(edm_ctx *ctx, const float *X, const int64_t *L, in
  * the workspace limit) the cross map's tables are derived from the sweep's:
  * at dimension E the Tp = 0 candidates are the Tp = 1 candidates plus the
  * point m1 = L - E, so a query's table is its sweep list with that point
- * offered last, and only query m1 needs a scan.  One stream sync (E_opt is
- * read back to group the targets).
+ * offered last, and only query m1 needs a scan.  The targets are grouped by
+ * E* on the device: the call never synchronises the stream, and with equal
+ * lengths it makes no host-to-device copy either, so it can be captured in a
+ * HIP graph (after one uncaptured call has grown the workspace).
  * X       : float32 [N][ldx] series, lengths L (host) [N]
  * rho_sweep, E_opt : as edm_simplex_sweep
  * rho     : float32 [N][N], rho[i][j] = library i, target j; NaN where the

@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libedm.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("EDM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["edm_api.hip", "knn.hip", "sweep_multi.hip", "gram.hip", "fixup.hip", "lookup.hip", "misc.hip", "net.hip", "plan.hip", "twokernel.hip", "subsample.hip", "noalloc.hip"]
+SOURCES = ["edm_api.hip", "knn.hip", "sweep_multi.hip", "gram.hip", "fixup.hip", "lookup.hip", "misc.hip", "net.hip", "plan.hip", "twokernel.hip", "subsample.hip", "noalloc.hip", "ceilings.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -47,9 +47,11 @@
 // * K-slots: lags 0..E_hi-1, one norm slot per E of the group, the threshold
 //   slot, zeros; a group that does not fit one 16-slot chunk shares a first
 //   chunk of lags 0..S-1 (S = min(E_lo, 16)) and keeps one chunk per E.
-// * Two passes over the candidate tiles.  Pass 1 samples one tile in eight
-//   and keeps, per lane and value slot, the candidate with the smallest
-//   hi*hi estimate at E_hi; the exact keys of a query's 32 slot winners bound
+// * Two passes over the candidate tiles.  Pass 1 visits every tile (BF16
+//   hi halves only, one product per chunk) and keeps, per lane and value
+//   slot, the candidate with the smallest hi*hi estimate at E_hi (one in
+//   m/32: the bound is near the true k-th key, so few candidates survive
+//   pass 2 before the lists fill); the exact keys of a query's 32 slot winners bound
 //   its final k-th key for every E of the group.  Pass 2 tests every tile:
 //   the OR over E of the estimates' sign bits is a per-lane mask, queued with
 //   the tile index in LDS without a branch; the queue is re-ranked when some
@@ -78,7 +80,7 @@ static_assert(kGramWaves * 32 == kKnnThreads, "a workgroup covers one query bloc
 constexpr float kGramScale = 1.0f - 0x1p-12f;  // s = 1 - 2^-12
 constexpr float kGramFloor = 0x1p-90f;          // absolute slack: flushed tiny products
 constexpr float kGramSafeMax = 0x1p56f;         // larger |x - mu| switches the filter off
-constexpr int kPass1Gap = 8 * 32;               // pass 1 samples one tile in eight
+constexpr int kPass1Gap = 32;                   // pass 1 visits every tile
 constexpr int kQueueCap = 16;                   // queued tile masks per lane before a re-rank
 constexpr float kGramBig = 0x1p120f;            // |threshold| cap: finite BF16 operands
 constexpr int kBufWord3 = 0x00020000;           // raw buffer resource, dword 3 (GFX9 family)
@@ -605,7 +607,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
 
   // Pass 1 (estimates only): lane v-slot b keeps the candidate with the
   // smallest estimate at E_hi (hi halves only, one product per chunk) among
-  // the sampled candidates kPass1Gap t + m(b); the 32 winners of
+  // the candidates kPass1Gap t + m(b); the 32 winners of
   // a query (16 per lane) are distinct candidates, so the K-th smallest of
   // their exact keys bounds the query's final K-th key from above, for every
   // E of the group.  These bounds cap the thresholds of pass 2 from the start.
@@ -620,7 +622,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     float bm[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) bm[v] = __builtin_inff();
-    // Every eighth tile (candidates kPass1Gap s + m(b)), two tiles per step
+    // Every tile (candidates kPass1Gap s + m(b)), two tiles per step
     // so that independent product chains overlap their latency.  A second
     // tile past the end repeats the first (same minimum).
     auto hi_tile = [&](int c0, const uint32_t (&nrv)[NG]) {

@@ -48,7 +48,7 @@ EXPORTS = (
     "edm_select_E",
     "edm_tune_default", "edm_ccm_plan_create", "edm_ccm_plan_run", "edm_ccm_plan_destroy",
     "edm_ctx_set_timing", "edm_ctx_timing", "edm_ctx_set_exclusion_radius", "edm_ccm_subsample",
-    "edm_simplex_sweep_noalloc",
+    "edm_simplex_sweep_noalloc", "edm_ceilings",
 )
 
 # kernel families of edm_ctx_timing (include/edm.h, EDM_KF_*)
@@ -118,6 +118,7 @@ def load_library(path: str = LIB_PATH):
         lib.edm_ctx_set_timing.argtypes = [_p, ctypes.c_int]
         lib.edm_ctx_timing.argtypes = [_p, _p, _p]
         lib.edm_ctx_set_exclusion_radius.argtypes = [_p, _i32]
+        lib.edm_ceilings.argtypes = [_p, _p, _p, _p]
         lib.edm_simplex_sweep_noalloc.argtypes = [_p, _p, _p, _i64, _i64, _i32, _i32, _i32, _p, _p]
         lib.edm_ccm_subsample.argtypes = [_p, _p, _i64, _p, _i64, _i64, _i32, _i32, _i32, _p, _p,
                                           _i64, _p, _p]
@@ -200,6 +201,13 @@ class Context:
         cnt = (ctypes.c_int64 * n)()
         _check(load_library().edm_ctx_timing(self._h, ctypes.cast(ms, _p), ctypes.cast(cnt, _p)), self._h)
         return {f: (float(ms[i]), int(cnt[i])) for i, f in enumerate(KERNEL_FAMILIES)}
+
+    def ceilings(self):
+        """Measured device ceilings (edm_ceilings): HBM GB/s, BF16 MFMA TFLOP/s,
+        float32 VALU T ops/s."""
+        v = [ctypes.c_double(0.0) for _ in range(3)]
+        _check(load_library().edm_ceilings(self._h, *[ctypes.byref(x) for x in v]), self._h)
+        return {"hbm_copy_GBps": v[0].value, "mfma_bf16_TFLOPs": v[1].value, "valu_fp32_Tops": v[2].value}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

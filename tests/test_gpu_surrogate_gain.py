@@ -6,6 +6,8 @@ proposals are verified by the simplex skill (edm_select_E), and the sweep
 judges the result: the E-selection time against the full sweep, and the rho
 lost where the verified E is not the sweep's E*.  A frequency prior (the m
 most common training labels for every series) is the no-network reference.
+With the confidence fallback calibrated on held-out training series, the
+least confident series take the full sweep and the worst loss shrinks.
 """
 import time
 
@@ -32,7 +34,8 @@ def test_surrogate_gain():
     rho_s, E_s = edm.edm_simplex_sweep(Xd, E_max=20, Tp=1, ctx=ctx)
     ctx.sync()
     sur = Surrogate(C=64, seed=0, ctx=ctx)
-    hist = sur.train(Xd[:N_tr], E_s[:N_tr], epochs=6, batch=128, lr=2e-3,
+    n_val = 1000  # held out of training, for the fallback's calibration
+    hist = sur.train(Xd[:N_tr - n_val], E_s[:N_tr - n_val], epochs=6, batch=128, lr=2e-3,
                      log=lambda m: print(m, flush=True))
     assert hist[-1][0] < hist[0][0]
     Xte, Ete = Xd[N_tr:].contiguous(), E_s[N_tr:].contiguous()
@@ -54,7 +57,7 @@ def test_surrogate_gain():
     loss_net = best - got
 
     # no-network reference: the m most frequent training labels for everyone
-    counts = np.bincount(E_s[:N_tr].cpu().numpy(), minlength=21)[1:]
+    counts = np.bincount(E_s[:N_tr - n_val].cpu().numpy(), minlength=21)[1:]
     prior = np.argsort(-counts, kind="stable")[:m_top] + 1
     got_prior = np.nanmax(rs[:, prior - 1], axis=1)
     loss_prior = best - got_prior
@@ -69,3 +72,21 @@ def test_surrogate_gain():
     assert loss_net.mean() < loss_prior.mean()
     assert exact > 0.5
     assert t_sel < t_sweep
+
+    # the confidence fallback: min_conf chosen on the held-out series so that
+    # none of them loses more than 0.01 of rho, then used on the test set
+    min_conf = sur.calibrate(Xd[N_tr - n_val:N_tr].contiguous(), rho_s[N_tr - n_val:N_tr].contiguous(),
+                             m_top=m_top, max_loss=0.01)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, e_fb, nfb_fb = sur.select_E(Xte, m_top=m_top, min_conf=min_conf)
+    ctx.sync()
+    t_fb = time.perf_counter() - t0
+    loss_fb = best - rs[np.arange(N_te), e_fb.cpu().numpy() - 1]
+    print(f"fallback at min_conf {min_conf:.3f}: {nfb_fb} of {N_te} series take the full sweep; "
+          f"{t_fb*1e3:.1f} ms ({t_sweep / t_fb:.2f}x); rho loss mean {loss_fb.mean():.2e} "
+          f"max {loss_fb.max():.2e} (without: max {loss_net.max():.2e})")
+    assert 0 < nfb_fb < N_te
+    assert np.all(loss_fb >= -1e-7)
+    assert loss_fb.max() <= loss_net.max() and loss_fb.mean() <= loss_net.mean()
+    assert t_fb < t_sweep

@@ -31,3 +31,14 @@ def test_timing_attributes_launches_to_families():
     edm.edm_simplex_sweep(Xd, E_max=8, ctx=ctx)
     assert all(n == 0 for _, n in ctx.timing().values())
     ctx.close()
+
+
+def test_ceilings_are_plausible():
+    ctx = edm.Context(device=0)
+    c = ctx.ceilings()
+    # a streaming copy reaches a sizeable share of the 8 TB/s HBM, the matrix
+    # cores a sizeable share of the 2.5 PFLOP/s BF16 peak; neither exceeds it
+    assert 1000.0 < c["hbm_copy_GBps"] <= 8000.0, c
+    assert 500.0 < c["mfma_bf16_TFLOPs"] <= 2500.0, c
+    assert 5.0 < c["valu_fp32_Tops"] <= 157.3, c
+    ctx.close()
