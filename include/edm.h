@@ -388,6 +388,9 @@ int edm_net_adam(edm_ctx *ctx, float *params, const float *grad, float *m, float
  * logits: float32 [N][20] (device); rho: float32 [N][E_max] (device), NaN
  * where E was not evaluated or is infeasible; E_opt: int32 [N] (device);
  * n_fallback (host, or NULL): number of series that took the full sweep.
+ * In EDM_FORM_CHOSEN and EDM_FORM_BATCHED (tau = 1, no exclusion radius)
+ * the series with every E to evaluate run the batched sweep (their rows are
+ * packed in the workspace); the others one exact scan per candidate E.
  * Synchronises the stream once (the candidate sets are read back). */
 int edm_select_E(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int64_t ldx,
                  int32_t E_max, int32_t tau, int32_t Tp, const float *logits, int32_t m_top,

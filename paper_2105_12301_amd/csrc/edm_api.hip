@@ -207,6 +207,60 @@ namespace host {
 
 using namespace edm::host;
 
+
+// The batched sweep (tau = 1, no exclusion window) of N contiguous rows: one
+// candidate scan per group of E values, through the matrix-core filter for
+// E >= 5 in the chosen form, co-moments into mom[N][E_max][mom_blocks].
+// plan() reserves the filter's norm buffers (rows in batches of at most
+// 1 GiB) in the caller's workspace plan; run() enqueues the scans.
+namespace {
+struct BatchedSweep {
+  bool gram = false;
+  int64_t L_max = 0, g_ld = 0, g_batch = 0;
+  size_t off_gmu = 0, off_gnrm = 0;
+
+  void plan(const edm_ctx *c, Plan &p, int64_t N, int64_t Lmax, int32_t E_max) {
+    L_max = Lmax;
+    gram = c->form == EDM_FORM_CHOSEN && E_max >= edm::kGramEMin && L_max <= edm::kGramLMax;
+    if (!gram) return;
+    g_ld = edm::gram_ld(L_max);
+    const size_t g_row = sizeof(uint32_t) * static_cast<size_t>(edm::kGramNE) * g_ld + sizeof(float);
+    g_batch = std::max<int64_t>(1, std::min<int64_t>(N, static_cast<int64_t>((size_t(1) << 30) / g_row)));
+    off_gmu = p.take(sizeof(float) * g_batch);
+    off_gnrm = p.take(sizeof(uint32_t) * static_cast<size_t>(edm::kGramNE) * g_ld * g_batch);
+  }
+
+  int run(edm_ctx *c, const float *X, int64_t ldx, const int64_t *L, const int64_t *L_dev, int64_t N,
+          int32_t E_max, int32_t Tp, edm::Mom *mom, int32_t mom_blocks) {
+    const int64_t step = gram ? g_batch : N;
+    for (int64_t b0 = 0; b0 < N; b0 += step) {
+      const int64_t nb = std::min<int64_t>(step, N - b0);
+      edm::KnnArgs a{};
+      a.X = X + b0 * ldx;
+      a.ldx = ldx;
+      a.L_dev = L_dev + b0;
+      a.Tp = Tp;
+      a.tau = 1;
+      a.mom = reinterpret_cast<edm::Mom *>(reinterpret_cast<char *>(mom) +
+                                           edm::kMomBytes * static_cast<size_t>(b0 * E_max) * mom_blocks);
+      a.mom_blocks = mom_blocks;
+      a.E_max = E_max;
+      a.status = c->status;
+      int64_t L_b = L_max;
+      if (gram) {
+        L_b = *std::max_element(L + b0, L + b0 + nb);
+        a.gram_mu = reinterpret_cast<float *>(c->ws + off_gmu);
+        a.gram_nrm = reinterpret_cast<uint32_t *>(c->ws + off_gnrm);
+        a.gram_ld = g_ld;
+        EDM_HIP(c, edm::launch_gram_prep(a, static_cast<int>(nb), L_b, c->stream));
+      }
+      EDM_HIP(c, edm::launch_sweep_multi(a, static_cast<int>(nb), L_b, c->stream));
+    }
+    return EDM_OK;
+  }
+};
+}  // namespace
+
 extern "C" {
 
 int edm_ctx_create(edm_ctx **out, void *hip_stream) {
@@ -426,53 +480,18 @@ int edm_simplex_sweep(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N,
   const int32_t mom_blocks = static_cast<int32_t>((L_max + edm::kKnnThreads - 1) / edm::kKnnThreads);
   const bool batched =
       (ctx->form == EDM_FORM_CHOSEN || ctx->form == EDM_FORM_BATCHED) && tau == 1 && ctx->excl == 0;
-  const bool gram = batched && ctx->form == EDM_FORM_CHOSEN && E_max >= edm::kGramEMin &&
-                    L_max <= edm::kGramLMax;
-  const int64_t g_ld = edm::gram_ld(L_max);
-  const size_t g_row = sizeof(uint32_t) * static_cast<size_t>(edm::kGramNE) * g_ld + sizeof(float);
   Plan plan;
   const size_t off_L = plan.take(sizeof(int64_t) * N);
   const size_t off_mom = plan.take(edm::kMomBytes * static_cast<size_t>(N) * E_max * mom_blocks);
-  // Filter norms for a batch of rows (at most 1 GiB, at least one row).
-  int64_t g_batch = 0;
-  size_t off_gmu = 0, off_gnrm = 0;
-  if (gram) {
-    g_batch = std::max<int64_t>(1, std::min<int64_t>(N, static_cast<int64_t>((size_t(1) << 30) / g_row)));
-    off_gmu = plan.take(sizeof(float) * g_batch);
-    off_gnrm = plan.take(sizeof(uint32_t) * static_cast<size_t>(edm::kGramNE) * g_ld * g_batch);
-  }
+  BatchedSweep bs;
+  if (batched) bs.plan(ctx, plan, N, L_max, E_max);
   if (plan.bytes > workspace_limit()) return set_err(ctx, EDM_E_NOMEM, "sweep workspace exceeds EDM_WORKSPACE_LIMIT");
   EDM_RC(ws_reserve(ctx, plan.bytes));
   int64_t *L_dev = reinterpret_cast<int64_t *>(ctx->ws + off_L);
   edm::Mom *mom = reinterpret_cast<edm::Mom *>(ctx->ws + off_mom);
   EDM_RC(upload(ctx, L, sizeof(int64_t) * N, L_dev));
   if (batched) {
-    // Batched form: one candidate scan per group of E values (through the
-    // matrix-core filter for E >= 5 in the chosen form).
-    const int64_t step = gram ? g_batch : N;
-    for (int64_t b0 = 0; b0 < N; b0 += step) {
-      const int64_t nb = std::min<int64_t>(step, N - b0);
-      edm::KnnArgs a{};
-      a.X = X + b0 * ldx;
-      a.ldx = ldx;
-      a.L_dev = L_dev + b0;
-      a.Tp = Tp;
-      a.tau = 1;
-      a.mom = reinterpret_cast<edm::Mom *>(reinterpret_cast<char *>(mom) +
-                                           edm::kMomBytes * static_cast<size_t>(b0 * E_max) * mom_blocks);
-      a.mom_blocks = mom_blocks;
-      a.E_max = E_max;
-      a.status = ctx->status;
-      int64_t L_b = L_max;
-      if (gram) {
-        L_b = *std::max_element(L + b0, L + b0 + nb);
-        a.gram_mu = reinterpret_cast<float *>(ctx->ws + off_gmu);
-        a.gram_nrm = reinterpret_cast<uint32_t *>(ctx->ws + off_gnrm);
-        a.gram_ld = g_ld;
-        EDM_HIP(ctx, edm::launch_gram_prep(a, static_cast<int>(nb), L_b, ctx->stream));
-      }
-      EDM_HIP(ctx, edm::launch_sweep_multi(a, static_cast<int>(nb), L_b, ctx->stream));
-    }
+    EDM_RC(bs.run(ctx, X, ldx, L, L_dev, N, E_max, Tp, mom, mom_blocks));
   } else {
   for (int E = 1; E <= E_max; ++E) {
     edm::KnnArgs a{};
@@ -1006,38 +1025,82 @@ int edm_select_E(edm_ctx *ctx, const float *X, const int64_t *L, int64_t N, int6
   if (N > INT32_MAX) return set_err(ctx, EDM_E_ARG, "too many series");
   const int64_t L_max = *std::max_element(L, L + N);
   const int32_t mom_blocks = static_cast<int32_t>((L_max + edm::kKnnThreads - 1) / edm::kKnnThreads);
+  const bool batched =
+      (ctx->form == EDM_FORM_CHOSEN || ctx->form == EDM_FORM_BATCHED) && tau == 1 && ctx->excl == 0;
+  const size_t mom_row = edm::kMomBytes * static_cast<size_t>(E_max) * mom_blocks;
   Plan plan;
   const size_t off_L = plan.take(sizeof(int64_t) * N);
-  const size_t off_ids = plan.take(sizeof(int32_t) * static_cast<size_t>(N) * E_max);
+  const size_t off_ids = plan.take(sizeof(int32_t) * static_cast<size_t>(N) * (E_max + 1));
   const size_t off_cand = plan.take(sizeof(uint32_t) * N);
-  const size_t off_mom = plan.take(edm::kMomBytes * static_cast<size_t>(N) * E_max * mom_blocks);
+  const size_t off_mom = plan.take(mom_row * N);
   if (plan.bytes > workspace_limit()) return set_err(ctx, EDM_E_NOMEM, "selection workspace exceeds EDM_WORKSPACE_LIMIT");
   EDM_RC(ws_reserve(ctx, plan.bytes));
-  int64_t *L_dev = reinterpret_cast<int64_t *>(ctx->ws + off_L);
-  int32_t *ids_dev = reinterpret_cast<int32_t *>(ctx->ws + off_ids);
-  uint32_t *cand = reinterpret_cast<uint32_t *>(ctx->ws + off_cand);
-  edm::Mom *mom = reinterpret_cast<edm::Mom *>(ctx->ws + off_mom);
-  EDM_RC(upload(ctx, L, sizeof(int64_t) * N, L_dev));
-  EDM_HIP(ctx, edm::launch_candidates(logits, N, E_max, m_top, min_conf, cand, ctx->stream));
+  EDM_RC(upload(ctx, L, sizeof(int64_t) * N, ctx->ws + off_L));
+  EDM_HIP(ctx, edm::launch_candidates(logits, N, E_max, m_top, min_conf,
+                                      reinterpret_cast<uint32_t *>(ctx->ws + off_cand), ctx->stream));
   std::vector<uint32_t> ch(static_cast<size_t>(N));
-  EDM_HIP(ctx, hipMemcpyAsync(ch.data(), cand, sizeof(uint32_t) * N, hipMemcpyDeviceToHost, ctx->stream));
+  EDM_HIP(ctx, hipMemcpyAsync(ch.data(), ctx->ws + off_cand, sizeof(uint32_t) * N, hipMemcpyDeviceToHost,
+                              ctx->stream));
   EDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
   const uint32_t all = (E_max >= 32) ? 0xffffffffu : ((1u << E_max) - 1u);
-  std::vector<int32_t> ids;
-  ids.reserve(static_cast<size_t>(N) * 2);
-  std::vector<int64_t> at(E_max + 2, 0);
   int64_t fb = 0;
   for (int64_t s = 0; s < N; ++s) fb += (ch[static_cast<size_t>(s)] == all && m_top < E_max);
+  // In the batched forms a series with every E to evaluate (the fallback)
+  // takes the batched sweep: its rows are packed, swept, and their
+  // co-moments scattered back.  The others run one exact scan per proposed E.
+  std::vector<int32_t> full;
+  if (batched)
+    for (int64_t s = 0; s < N; ++s)
+      if (ch[static_cast<size_t>(s)] == all) full.push_back(static_cast<int32_t>(s));
+  const int64_t n_full = static_cast<int64_t>(full.size());
+  std::vector<int32_t> ids(full);
+  std::vector<int64_t> at(E_max + 2, 0);
   for (int E = 1; E <= E_max; ++E) {
     at[E] = static_cast<int64_t>(ids.size());
     for (int64_t s = 0; s < N; ++s) {
+      const uint32_t c = ch[static_cast<size_t>(s)];
       const int64_t m = L[s] - static_cast<int64_t>(E - 1) * tau - Tp;
-      if (((ch[static_cast<size_t>(s)] >> (E - 1)) & 1u) && m - 1 - 2 * ctx->excl >= E + 1)
+      if (((c >> (E - 1)) & 1u) && !(batched && c == all) && m - 1 - 2 * ctx->excl >= E + 1)
         ids.push_back(static_cast<int32_t>(s));
     }
   }
   at[E_max + 1] = static_cast<int64_t>(ids.size());
+  // the packed rows of the fallback series, their lengths and co-moments
+  BatchedSweep bs;
+  size_t off_X = 0, off_Lf = 0, off_momf = 0;
+  std::vector<int64_t> Lf(static_cast<size_t>(n_full));
+  for (int64_t i = 0; i < n_full; ++i) Lf[static_cast<size_t>(i)] = L[full[static_cast<size_t>(i)]];
+  if (n_full > 0) {
+    off_X = plan.take(sizeof(float) * static_cast<size_t>(L_max) * n_full);
+    off_Lf = plan.take(sizeof(int64_t) * n_full);
+    off_momf = plan.take(mom_row * n_full);
+    bs.plan(ctx, plan, n_full, L_max, E_max);
+    if (plan.bytes > workspace_limit())
+      return set_err(ctx, EDM_E_NOMEM, "selection workspace exceeds EDM_WORKSPACE_LIMIT");
+    // a larger workspace is a new allocation (the stream is idle): the
+    // lengths and candidate sets go up again
+    const bool moved = plan.bytes > ctx->ws_bytes;
+    EDM_RC(ws_reserve(ctx, plan.bytes));
+    if (moved) {
+      EDM_RC(upload(ctx, L, sizeof(int64_t) * N, ctx->ws + off_L));
+      EDM_RC(upload(ctx, ch.data(), sizeof(uint32_t) * N, ctx->ws + off_cand));
+    }
+  }
+  int64_t *L_dev = reinterpret_cast<int64_t *>(ctx->ws + off_L);
+  int32_t *ids_dev = reinterpret_cast<int32_t *>(ctx->ws + off_ids);
+  const uint32_t *cand = reinterpret_cast<const uint32_t *>(ctx->ws + off_cand);
+  edm::Mom *mom = reinterpret_cast<edm::Mom *>(ctx->ws + off_mom);
   if (!ids.empty()) EDM_RC(upload(ctx, ids.data(), sizeof(int32_t) * ids.size(), ids_dev));
+  if (n_full > 0) {
+    float *Xf = reinterpret_cast<float *>(ctx->ws + off_X);
+    int64_t *Lf_dev = reinterpret_cast<int64_t *>(ctx->ws + off_Lf);
+    edm::Mom *momf = reinterpret_cast<edm::Mom *>(ctx->ws + off_momf);
+    EDM_RC(upload(ctx, Lf.data(), sizeof(int64_t) * n_full, Lf_dev));
+    EDM_HIP(ctx, edm::launch_copy_rows(X, ldx, Xf, L_max, ids_dev, n_full, L_max, false, ctx->stream));
+    EDM_RC(bs.run(ctx, Xf, L_max, Lf.data(), Lf_dev, n_full, E_max, Tp, momf, mom_blocks));
+    const int64_t mw = static_cast<int64_t>(mom_row / sizeof(uint32_t));
+    EDM_HIP(ctx, edm::launch_copy_rows(momf, mw, mom, mw, ids_dev, n_full, mw, true, ctx->stream));
+  }
   for (int E = 1; E <= E_max; ++E) {
     const int64_t n_E = at[E + 1] - at[E];
     if (n_E == 0) continue;

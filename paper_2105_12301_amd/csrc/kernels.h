@@ -245,6 +245,10 @@ hipError_t launch_group_by_E(const int32_t *E, int64_t N, int32_t E_max, int32_t
 // set, n_tgt_max bounds the bucket (for the tile size).
 hipError_t launch_lookup_bucket(const LookupArgs &a, int nslots, int64_t m_max, int64_t n_tgt_max,
                                 hipStream_t st);
+// Rows of `words` 32-bit words: gather dst[i] = src[ids[i]] or scatter
+// dst[ids[i]] = src[i], i < n; leading dimensions in words.
+hipError_t launch_copy_rows(const void *src, int64_t lds, void *dst, int64_t ldd, const int32_t *ids,
+                            int64_t n, int64_t words, bool scatter, hipStream_t st);
 hipError_t launch_embed(const float *x, int64_t L, int32_t E, int32_t tau, float *out,
                         int *status, hipStream_t st);
 

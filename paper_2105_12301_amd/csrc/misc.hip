@@ -139,6 +139,20 @@ __global__ void k_fill(float *__restrict__ p, int64_t n, float v) {
 }
 
 // out[p][j] = x[p + j*tau]; consecutive threads write consecutive elements.
+// Row copy between a row subset of one array and a packed array:
+// gather: dst[i] = src[ids[i]], scatter: dst[ids[i]] = src[i] (rows of
+// `words` 32-bit words, leading dimensions in words).
+__global__ void k_copy_rows(const uint32_t *__restrict__ src, int64_t lds, uint32_t *__restrict__ dst,
+                            int64_t ldd, const int32_t *__restrict__ ids, int64_t words, int scatter) {
+  const int64_t i = blockIdx.y;
+  const int64_t r = ids[i];
+  const uint32_t *s = src + (scatter ? i : r) * lds;
+  uint32_t *d = dst + (scatter ? r : i) * ldd;
+  for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
+       w += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    d[w] = s[w];
+}
+
 __global__ void k_embed(const float *__restrict__ x, int64_t n, int32_t E, int32_t tau,
                         float *__restrict__ out, int *status) {
   const int64_t total = n * E;
@@ -203,6 +217,25 @@ hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t st) {
   TimedLaunch timed(EDM_KF_OTHER, st);
   hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(const void *src, int64_t lds, void *dst, int64_t ldd, const int32_t *ids,
+                            int64_t n, int64_t words, bool scatter, hipStream_t st) {
+  if (n <= 0 || words <= 0) return hipSuccess;
+  TimedLaunch timed(EDM_KF_OTHER, st);
+  const int64_t wb = (words + 255) / 256;
+  const unsigned gx = static_cast<unsigned>(wb < 64 ? wb : 64);
+  constexpr int64_t kMaxY = 32768;
+  for (int64_t c0 = 0; c0 < n; c0 += kMaxY) {  // packed side offset by c0 rows
+    const int64_t nc = n - c0 < kMaxY ? n - c0 : kMaxY;
+    const uint32_t *s = static_cast<const uint32_t *>(src) + (scatter ? c0 * lds : 0);
+    uint32_t *d = static_cast<uint32_t *>(dst) + (scatter ? 0 : c0 * ldd);
+    hipLaunchKernelGGL(k_copy_rows, dim3(gx, static_cast<unsigned>(nc)), dim3(256), 0, st, s, lds, d, ldd,
+                       ids + c0, words, scatter ? 1 : 0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_embed(const float *x, int64_t L, int32_t E, int32_t tau, float *out,

@@ -139,3 +139,31 @@ def test_select_top1_evaluates_only_the_proposal(edm, ctx):
     for s in range(16):
         assert np.array_equal(np.isnan(r[s]), np.arange(1, 21) != prop[s])
         assert r[s, prop[s] - 1] == rs[s, prop[s] - 1]
+
+
+@pytest.mark.parametrize("form", ["chosen", "batched"])
+def test_select_mixed_fallback_batched_form(edm, form):
+    # Even series get one confident proposal; odd series uniform logits, below
+    # min_conf, so they take the full sweep, which the batched forms run on
+    # packed rows (uneven lengths) and scatter back.
+    N = 40
+    X, _ = synth.surrogate_mix(seed=13, N=N, L=700)
+    lens = np.random.default_rng(13).integers(300, 701, size=N)
+    Xd = dev(X)
+    prop = np.arange(N) % 20 + 1
+    logits = np.zeros((N, 20), np.float32)
+    ev = np.arange(0, N, 2)
+    logits[ev, prop[ev] - 1] = 8.0
+    c = edm.Context(device=0, form=getattr(edm, f"EDM_FORM_{form.upper()}"))
+    rs, es = edm.edm_simplex_sweep(Xd, lengths=lens, E_max=20, ctx=c)
+    r, e, nfb = edm.edm_select_E(Xd, dev(logits), lengths=lens, E_max=20, m_top=1, min_conf=0.5, ctx=c)
+    c.sync()
+    r, e, rs, es = r.cpu().numpy(), e.cpu().numpy(), rs.cpu().numpy(), es.cpu().numpy()
+    c.close()
+    assert nfb == N // 2
+    for s in range(N):
+        if s % 2:
+            assert np.array_equal(r[s].view(np.int32), rs[s].view(np.int32)) and e[s] == es[s]
+        else:
+            assert np.array_equal(np.isnan(r[s]), np.arange(1, 21) != prop[s])
+            assert r[s, prop[s] - 1] == rs[s, prop[s] - 1] and e[s] == prop[s]
