@@ -33,6 +33,9 @@
 //
 // Layout on the chip
 // ------------------
+// * Grid: workgroups are dispatched round-robin over the 8 dies (one L2
+//   each); the query blocks of one series are mapped to one die, so its
+//   samples and norms are fetched into one L2 and shared there.
 // * Workgroup = 8 waves = the 256 queries of one exact-scan block; LDS holds
 //   the BF16 hi and lo halves of the centred series (matrix operands), the
 //   float32 series (exact re-rank, weights) up to kGramLdsXsMax samples
@@ -80,8 +83,9 @@ static_assert(kGramWaves * 32 == kKnnThreads, "a workgroup covers one query bloc
 constexpr float kGramScale = 1.0f - 0x1p-12f;  // s = 1 - 2^-12
 constexpr float kGramFloor = 0x1p-90f;          // absolute slack: flushed tiny products
 constexpr float kGramSafeMax = 0x1p56f;         // larger |x - mu| switches the filter off
-constexpr int kPass1Gap = 32;                   // pass 1 visits every tile
+constexpr int kP1Tiles = 4;                     // pass-1 tiles per step
 constexpr int kQueueCap = 16;                   // queued tile masks per lane before a re-rank
+constexpr int kGramXcds = 8;                    // accelerator dies (one L2 each), round-robin dispatch
 constexpr float kGramBig = 0x1p120f;            // |threshold| cap: finite BF16 operands
 constexpr int kBufWord3 = 0x00020000;           // raw buffer resource, dword 3 (GFX9 family)
 
@@ -116,11 +120,15 @@ __device__ __forceinline__ void read_window(const uint32_t *__restrict__ w32, in
   for (int i = 0; i < 4; ++i) out[i] = __builtin_amdgcn_alignbit(W[i + 1], W[i], sh);
 }
 
-// Minimum of two finite floats, one instruction (no NaN canonicalisation).
-__device__ __forceinline__ float vmin(float a, float b) {
-  float r;
-  asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
+// Minimum of two floats as the median of (a, b, -inf): one instruction and
+// no NaN canonicalisation (the operands are finite or +inf).
+__device__ __forceinline__ float min2(float a, float b) {
+  return __builtin_amdgcn_fmed3f(a, b, -__builtin_inff());
+}
+
+// e with its 10 low mantissa bits replaced by t (t < 1024).
+__device__ __forceinline__ float with_low10(float e, uint32_t t) {
+  return __uint_as_float((__float_as_uint(e) & 0xfffffc00u) | t);
 }
 
 // Ascending bitonic sort of 32 values held in registers.
@@ -607,7 +615,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
 
   // Pass 1 (estimates only): lane v-slot b keeps the candidate with the
   // smallest estimate at E_hi (hi halves only, one product per chunk) among
-  // the candidates kPass1Gap t + m(b); the 32 winners of
+  // the candidates 32 t + m(b); the 32 winners of
   // a query (16 per lane) are distinct candidates, so the K-th smallest of
   // their exact keys bounds the query's final K-th key from above, for every
   // E of the group.  These bounds cap the thresholds of pass 2 from the start.
@@ -622,9 +630,6 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     float bm[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) bm[v] = __builtin_inff();
-    // Every tile (candidates kPass1Gap s + m(b)), two tiles per step
-    // so that independent product chains overlap their latency.  A second
-    // tile past the end repeats the first (same minimum).
     auto hi_tile = [&](int c0, const uint32_t (&nrv)[NG]) {
       uint32_t a_h[NCH][4];
       static_for<0, NCH - 1>([&](auto CC) {
@@ -640,34 +645,41 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
       for (int C = C0; C < NCH; ++C) acc = mfma(a_h[C], bh[NG - 1][C - C0], acc);
       return acc;
     };
-    uint32_t nA[NG], nB[NG];
-    auto fetch2 = [&](int c0) {  // in bounds: c0 < m_lo + 64 <= gram_ld
-      const int cb = c0 + kPass1Gap < m_lo ? c0 + kPass1Gap : c0;
+    // kP1Tiles tiles per step, their norms loaded one step ahead, so that
+    // independent product chains and the loads overlap their latency.  Tiles
+    // past the end repeat the step's first tile (same minimum).
+    uint32_t nN[kP1Tiles][NG];
+    auto fetchN = [&](int c0) {  // in bounds: every tile start is below m_lo
 #pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        nA[g] = nrm[g * ld + c0 + n];
-        nB[g] = nrm[g * ld + cb + n];
+      for (int t = 0; t < kP1Tiles; ++t) {
+        const int c = c0 + 32 * t < m_lo ? c0 + 32 * t : c0;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) nN[t][g] = nrm[g * ld + c + n];
       }
     };
-    fetch2(0);
+    fetchN(0);
 #pragma unroll 1
-    for (int c0 = 0; c0 < m_lo; c0 += 2 * kPass1Gap) {
-      const int cb = c0 + kPass1Gap < m_lo ? c0 + kPass1Gap : c0;
-      uint32_t na[NG], nb[NG];
+    for (int c0 = 0; c0 < m_lo; c0 += 32 * kP1Tiles) {
+      uint32_t nc[kP1Tiles][NG];
 #pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        na[g] = nA[g];
-        nb[g] = nB[g];
+      for (int t = 0; t < kP1Tiles; ++t)
+#pragma unroll
+        for (int g = 0; g < NG; ++g) nc[t][g] = nN[t][g];
+      if (c0 + 32 * kP1Tiles < m_lo) fetchN(c0 + 32 * kP1Tiles);
+      f32x16_t acc[kP1Tiles];
+      uint32_t tix[kP1Tiles];
+#pragma unroll
+      for (int t = 0; t < kP1Tiles; ++t) {
+        const int c = c0 + 32 * t < m_lo ? c0 + 32 * t : c0;
+        acc[t] = hi_tile(c, nc[t]);
+        tix[t] = static_cast<uint32_t>(c) >> 5;
       }
-      if (c0 + 2 * kPass1Gap < m_lo) fetch2(c0 + 2 * kPass1Gap);
-      const f32x16_t accA = hi_tile(c0, na);
-      const f32x16_t accB = hi_tile(cb, nb);
-      const uint32_t tA = static_cast<uint32_t>(c0) >> 5, tB = static_cast<uint32_t>(cb) >> 5;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const float eA = __uint_as_float((__float_as_uint(accA[v]) & ~0x3ffu) | tA);
-        const float eB = __uint_as_float((__float_as_uint(accB[v]) & ~0x3ffu) | tB);
-        bm[v] = vmin(bm[v], vmin(eA, eB));
+        float e = with_low10(acc[0][v], tix[0]);
+#pragma unroll
+        for (int t = 1; t < kP1Tiles; ++t) e = min2(e, with_low10(acc[t][v], tix[t]));
+        bm[v] = min2(bm[v], e);
       }
     }
     float kb[NG][16];
@@ -924,11 +936,18 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
   }
 }
 
+// One-dimensional grid over (slot, query block).  Workgroups are dispatched
+// round-robin over the kGramXcds dies, each with its own L2: workgroup i runs
+// on die i % kGramXcds, and the nblk query blocks of a slot are given to one
+// die, whose L2 then serves that slot's samples and norms to all of them.
 template <int ELO, int EHI, bool XG>
-__global__ __launch_bounds__(kGramThreads) void k_gram(KnnArgs a, int slot0) {
+__global__ __launch_bounds__(kGramThreads) void k_gram(KnnArgs a, int slot0, int nslots, int nblk) {
   extern __shared__ float gram_smem[];
-  gram_scan<ELO, EHI, XG>(a, slot0 + static_cast<int>(blockIdx.y), static_cast<int>(blockIdx.x),
-                          gram_smem);
+  const int i = static_cast<int>(blockIdx.x);
+  const int x = i % kGramXcds, s = i / kGramXcds;
+  const int row = (s / nblk) * kGramXcds + x;
+  if (row >= nslots) return;  // padding of the last die round (uniform)
+  gram_scan<ELO, EHI, XG>(a, slot0 + row, s % nblk, gram_smem);
 }
 
 // Centring constant of each slot: the float32 mean (float64 sum).
@@ -981,7 +1000,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_items(KnnArgs a,
   gram_scan<ELO, EHI, XG>(a, row, blk, gram_smem);
 }
 
-using GramFn = void (*)(KnnArgs, int);
+using GramFn = void (*)(KnnArgs, int, int, int);
 
 template <int LO, int HI, bool XG>
 constexpr GramFn gram_fn() {
@@ -1087,12 +1106,13 @@ hipError_t launch_gram_group(const KnnArgs &a, int lo, int hi, int nslots, int64
                                        static_cast<int>(shm));
     if (e != hipSuccess) return e;
   }
-  const unsigned gx = static_cast<unsigned>((L_max + kKnnThreads - 1) / kKnnThreads);
+  const int nblk = static_cast<int>((L_max + kKnnThreads - 1) / kKnnThreads);
   TimedLaunch timed(EDM_KF_FILTER_SCAN, st);
-  constexpr int kMaxY = 32768;
-  for (int s0 = 0; s0 < nslots; s0 += kMaxY) {
-    const int ny = nslots - s0 < kMaxY ? nslots - s0 : kMaxY;
-    hipLaunchKernelGGL(fn, dim3(gx, static_cast<unsigned>(ny)), dim3(kGramThreads), shm, st, a, s0);
+  constexpr int kMaxSlots = 32768;
+  for (int s0 = 0; s0 < nslots; s0 += kMaxSlots) {
+    const int ny = nslots - s0 < kMaxSlots ? nslots - s0 : kMaxSlots;
+    const unsigned nwg = static_cast<unsigned>((ny + kGramXcds - 1) / kGramXcds * kGramXcds * nblk);
+    hipLaunchKernelGGL(fn, dim3(nwg), dim3(kGramThreads), shm, st, a, s0, ny, nblk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
