@@ -131,14 +131,14 @@ __device__ __forceinline__ float with_low10(float e, uint32_t t) {
   return __uint_as_float((__float_as_uint(e) & 0xfffffc00u) | t);
 }
 
-// Ascending bitonic sort of 32 values held in registers.
-__device__ __forceinline__ void sort32(float (&a)[32]) {
+// Ascending bitonic sort of 16 values held in registers.
+__device__ __forceinline__ void sort16(float (&a)[16]) {
 #pragma unroll
-  for (int k = 2; k <= 32; k <<= 1)
+  for (int k = 2; k <= 16; k <<= 1)
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1)
 #pragma unroll
-      for (int i = 0; i < 32; ++i) {
+      for (int i = 0; i < 16; ++i) {
         const int l = i ^ j;
         if (l > i) {
           const float x = a[i], y = a[l];
@@ -693,16 +693,27 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
 #pragma unroll
       for (int g = 0; g < NG; ++g) kb[g][v] = key[g];
     }
+    // K-th smallest (K = E + 1) of the 32 keys of the lane pair: each lane
+    // sorts its 16, and with A, B the two sorted halves (+inf past the end)
+    // the K-th smallest of their union is the largest min(A[i], B[K - 1 - i]).
     static_for<ELO, EHI>([&](auto EC) {
       constexpr int E = decltype(EC)::value;
-      float a[32];
+      constexpr int K = E + 1;
+      float a[16], b[16];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        a[v] = kb[E - ELO][v];
-        a[16 + v] = __shfl_xor(kb[E - ELO][v], 32);
+      for (int v = 0; v < 16; ++v) a[v] = kb[E - ELO][v];
+      sort16(a);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) b[v] = __shfl_xor(a[v], 32);
+      float u = -__builtin_inff();
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const int j = K - 1 - i;
+        if (i < 16 && j < 16) u = fmaxf(u, fminf(a[i], b[j]));
+        else if (i < 16) u = fmaxf(u, a[i]);
+        else u = fmaxf(u, b[j]);
       }
-      sort32(a);
-      ub[E - ELO] = a[E];  // K-th smallest, K = E + 1
+      ub[E - ELO] = u;
     });
   }
 
