@@ -316,6 +316,10 @@ typedef struct {
   int32_t lookup_wg_per_cu;   /* 0: one workgroup per lookup item; >0: persistent workgroups per CU */
   int32_t lookup_targets;     /* targets staged per lookup item, 1..16 (fewer where the
                                  longest library's window would pass 160 KB of LDS) */
+  int32_t filter_stride;      /* chosen form: the matrix-core filter's first pass visits one
+                                 candidate tile in filter_stride (1..8), which bounds each
+                                 query's k-th key; 0: by E group and series length.  Tables
+                                 and rho do not depend on it, only the time. */
 } edm_tune;
 
 void edm_tune_default(edm_tune *tune);

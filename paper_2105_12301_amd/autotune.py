@@ -1,8 +1,10 @@
-"""Autotuner for the launch shapes of the batched CCM plan (edm_tune).
+"""Autotuner for the batched CCM plan (edm_tune): launch shapes and, in the
+chosen form, the matrix-core filter's first-pass tile stride.
 
 Candidates are timed on a sample of libraries spread over the length range
 (every target kept), each on a fresh plan whose graph is captured by a first
-run; the fastest replay wins.  Results are cached in a JSON file (path from
+run; the fastest replay wins.  The search is coordinate-wise: the launch
+shapes with the filter's default stride, then the winner with each stride.  Results are cached in a JSON file (path from
 EDM_AUTOTUNE_CACHE, default ~/.cache/edm_autotune.json) keyed by the device
 name and a coarse shape class of the workload.
 """
@@ -17,9 +19,10 @@ import torch
 from . import edm
 
 CANDIDATES = [
-    dict(tables_wg_per_cu=t, lookup_wg_per_cu=l, lookup_targets=T)
+    dict(tables_wg_per_cu=t, lookup_wg_per_cu=l, lookup_targets=T, filter_stride=0)
     for t in (0, 1, 2) for l in (0, 4) for T in (4, 8, 16)
 ]
+FILTER_STRIDES = (1, 2, 4, 8)
 
 
 def _cache_path():
@@ -62,7 +65,11 @@ def autotune(X, Lx, Y, Ly, E, Tp: int = 0, ctx=None, sample: int = 48, reps: int
     Xs = X.index_select(0, torch.from_numpy(pick).to(X.device)).contiguous()
     rho = torch.empty((len(pick), Y.shape[0]), dtype=torch.float32, device=X.device)
     times = {}
-    for cand in CANDIDATES:
+
+    def name_of(c):
+        return ",".join(f"{k}={v}" for k, v in c.items())
+
+    def time_one(cand):
         plan = edm.CcmPlan(Lx[pick], Ly, E, Xs.shape[1], Y.shape[1], Tp=Tp, tune=make_tune(cand), ctx=ctx)
         plan.run(Xs, Y, rho)  # capture
         ctx.sync()
@@ -75,11 +82,18 @@ def autotune(X, Lx, Y, Ly, E, Tp: int = 0, ctx=None, sample: int = 48, reps: int
             ev1.synchronize()
             best = min(best, ev0.elapsed_time(ev1))
         plan.close()
-        name = ",".join(f"{k}={v}" for k, v in cand.items())
-        times[name] = best
+        times[name_of(cand)] = best
         if log:
-            log(f"  {name}: {best:.2f} ms")
-    win = min(CANDIDATES, key=lambda c: times[",".join(f"{k}={v}" for k, v in c.items())])
+            log(f"  {name_of(cand)}: {best:.2f} ms")
+
+    for cand in CANDIDATES:
+        time_one(cand)
+    win = min(CANDIDATES, key=lambda c: times[name_of(c)])
+    if getattr(ctx, "form", 0) == edm.EDM_FORM_CHOSEN:
+        strided = [dict(win, filter_stride=f) for f in FILTER_STRIDES]
+        for cand in strided:
+            time_one(cand)
+        win = min([win] + strided, key=lambda c: times[name_of(c)])
     if use_cache:
         cache[key] = {"tune": win, "times": times}
         os.makedirs(os.path.dirname(path), exist_ok=True)

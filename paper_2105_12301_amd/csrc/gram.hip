@@ -650,8 +650,9 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     // past the end repeat the step's first tile (same minimum).  Pass 1
     // visits one tile in `stride`: every tile gives the tightest bounds, a
     // sample costs less; measured per group on 2000-sample series, every
-    // fourth tile is faster for E 9-16 and for series above 4096 samples.
-    const int stride = ((ELO >= 9 && ELO <= 14) || m_lo > 4096) ? 4 : 1;
+    // fourth tile is faster for E 9-16 and for series above 4096 samples
+    // (the default; a batched plan may set its own from its autotuner).
+    const int stride = a.p1_stride > 0 ? a.p1_stride : (((ELO >= 9 && ELO <= 14) || m_lo > 4096) ? 4 : 1);
     uint32_t nN[kP1Tiles][NG];
     auto fetchN = [&](int c0) {  // in bounds: every tile start is below m_lo
 #pragma unroll

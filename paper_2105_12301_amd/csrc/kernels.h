@@ -37,6 +37,7 @@ struct KnnArgs {
   const int32_t *lib_ids;    // slot -> row of X (device) or nullptr -> row = slot
   int32_t E, tau, Tp, k;
   int32_t excl;              // exclusion radius: candidates with |q - p| <= excl are skipped
+  int32_t p1_stride;         // filter pass 1 visits one candidate tile in p1_stride (0: by group and length)
   int32_t *idx;              // [slot][nq][k] or nullptr
   float *dist;               // [slot][nq][k] or nullptr
   float *w;                  // [slot][nq][k] or nullptr

@@ -102,6 +102,7 @@ void edm_tune_default(edm_tune *t) {
   t->tables_wg_per_cu = 0;
   t->lookup_wg_per_cu = 0;
   t->lookup_targets = 16;
+  t->filter_stride = 0;
 }
 
 void edm_ccm_plan_destroy(edm_ctx *ctx, edm_plan *plan) {
@@ -131,7 +132,8 @@ int edm_ccm_plan_create(edm_ctx *ctx, const int64_t *Lx, int64_t Nl, int64_t ldx
   edm_tune_default(&tn);
   if (tune) tn = *tune;
   if (tn.tables_wg_per_cu < 0 || tn.tables_wg_per_cu > 8 || tn.lookup_wg_per_cu < 0 ||
-      tn.lookup_wg_per_cu > 16 || tn.lookup_targets < 1 || tn.lookup_targets > edm::kLookupItemMaxTargets)
+      tn.lookup_wg_per_cu > 16 || tn.lookup_targets < 1 || tn.lookup_targets > edm::kLookupItemMaxTargets ||
+      tn.filter_stride < 0 || tn.filter_stride > 8)
     return set_err(ctx, EDM_E_ARG, "tune out of range");
   EDM_RC(check_ctx(ctx));
   if (ctx->excl != 0) return set_err(ctx, EDM_E_ARG, "batched plans need exclusion radius 0");
@@ -382,6 +384,7 @@ int enqueue_plan(edm_ctx *ctx, edm_plan *P, const float *X, const float *Y, floa
                                                  P->n_cu, st));
     for (int h = 0; h < 2; ++h) {  // short libraries (LDS stride of the short ones), then long ones
       edm::KnnArgs ah = a;
+      ah.p1_stride = P->tune.filter_stride;
       const int64_t Lh = h == 0 ? B.Ls_max : B.Lg_max;
       ah.gram_lds = Lh > 0 ? edm::gram_ld(Lh) : 0;
       for (int f = 0; f < kNGram; ++f, ++c) {

@@ -59,7 +59,7 @@ KERNEL_FAMILIES = ("exact_scan", "batched_scan", "filter_prep", "filter_scan", "
 class Tune(ctypes.Structure):
     """Launch shapes of a batched CCM plan (edm_tune)."""
     _fields_ = [("tables_wg_per_cu", ctypes.c_int32), ("lookup_wg_per_cu", ctypes.c_int32),
-                ("lookup_targets", ctypes.c_int32)]
+                ("lookup_targets", ctypes.c_int32), ("filter_stride", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

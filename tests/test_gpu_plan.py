@@ -113,6 +113,37 @@ def test_chosen_plan_equals_plain_ccm_bitwise(edm, side, tune):
         ctx.close()
 
 
+@pytest.mark.parametrize("stride", [1, 3, 8])
+def test_chosen_plan_filter_stride_bitwise(edm, side, stride):
+    # The filter's first-pass tile stride (a tune field) changes only how
+    # tight the first bounds are: every rho equals the plain form's bit for
+    # bit, for series both shorter and longer than 4096 samples.
+    from paper_2105_12301_amd.autotune import make_tune
+    X, lens, E = synth.spike_trains(seed=24, N=24, L_min=300, L_max=6000)
+    E = np.where(E < 5, E + 8, E).astype(np.int32)   # every pair through the filter
+    with torch.cuda.stream(side):
+        ctx = edm.Context(device=0, stream=side, form=edm.EDM_FORM_PLAIN)
+        Xd = dev(X)
+        ref = edm.edm_ccm(Xd, dev(E), Lx=lens, Ly=lens, ctx=ctx)
+        ctx.set_form(edm.EDM_FORM_CHOSEN)
+        tune = make_tune(dict(TUNES[0], filter_stride=stride))
+        plan = edm.CcmPlan(lens, lens, E, X.shape[1], X.shape[1], tune=tune, ctx=ctx)
+        r1 = plan.run(Xd).clone()
+        ctx.sync()
+        assert torch.equal(ref.view(torch.int32), r1.view(torch.int32))
+        plan.close()
+        ctx.close()
+
+
+def test_plan_rejects_filter_stride_out_of_range(edm):
+    from paper_2105_12301_amd.autotune import make_tune
+    X, lens, E = synth.spike_trains(seed=25, N=8, L_min=300, L_max=600)
+    ctx = edm.Context(device=0)
+    with pytest.raises(edm.EdmError):
+        edm.CcmPlan(lens, lens, E, X.shape[1], X.shape[1], tune=make_tune(dict(TUNES[0], filter_stride=9)), ctx=ctx)
+    ctx.close()
+
+
 def test_plan_matches_oracle_and_default_stream(edm):
     X, lens, E = synth.spike_trains(seed=22, N=20, L_min=200, L_max=900)
     ctx = edm.Context(device=0)   # legacy stream: enqueued without a graph
@@ -137,4 +168,9 @@ def test_autotune_picks_a_candidate(edm, side, tmp_path, monkeypatch):
         assert len(times) == len(autotune.CANDIDATES)
         t2, _ = autotune.autotune(Xd, lens, Xd, lens, E, ctx=ctx, sample=8, reps=1)   # cached
         assert t.as_dict() == t2.as_dict()
+        # chosen form: the filter's first-pass stride is searched as well
+        ctx.set_form(edm.EDM_FORM_CHOSEN)
+        t3, times3 = autotune.autotune(Xd, lens, Xd, lens, E, ctx=ctx, sample=8, reps=1)
+        assert len(times3) == len(autotune.CANDIDATES) + len(autotune.FILTER_STRIDES)
+        assert t3.filter_stride in (0,) + autotune.FILTER_STRIDES
         ctx.close()
