@@ -508,7 +508,18 @@ def main(argv=None):
         wl = CALCIUM if args.workload == "calcium" else NETWORK
         out = bench_main(args, torch, edm, synth, wl, args.workload)
     print(json.dumps(out), flush=True)
+    _stop_helpers()
     return 0
+
+
+def _stop_helpers():
+    """Stop multiprocessing's resource tracker, which the spawned worker pools
+    of the CPU leg start, so that no helper process outlives the benchmark."""
+    try:
+        from multiprocessing import resource_tracker
+        resource_tracker._resource_tracker._stop()
+    except Exception:  # private interface: best effort only
+        pass
 
 
 # ------------------------------------------------------- variant workloads --
