@@ -516,7 +516,9 @@ def _stop_helpers():
     """Stop multiprocessing's resource tracker, which the spawned worker pools
     of the CPU leg start, so that no helper process outlives the benchmark."""
     try:
+        import gc
         from multiprocessing import resource_tracker
+        gc.collect()  # released pools unregister their semaphores first
         resource_tracker._resource_tracker._stop()
     except Exception:  # private interface: best effort only
         pass
