@@ -51,7 +51,7 @@
 //   slot, zeros; a group that does not fit one 16-slot chunk shares a first
 //   chunk of lags 0..S-1 (S = min(E_lo, 16)) and keeps one chunk per E.
 // * Two passes over the candidate tiles.  Pass 1 visits every tile, or one
-//   in four (BF16 hi halves only, one product per chunk) and keeps, per lane and value
+//   in three or four (BF16 hi halves only, one product per chunk) and keeps, per lane and value
 //   slot, the candidate with the smallest hi*hi estimate at E_hi (one in
 //   m/32: the bound is near the true k-th key, so few candidates survive
 //   pass 2 before the lists fill); the exact keys of a query's 32 slot winners bound
@@ -649,10 +649,12 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     // independent product chains and the loads overlap their latency.  Tiles
     // past the end repeat the step's first tile (same minimum).  Pass 1
     // visits one tile in `stride`: every tile gives the tightest bounds, a
-    // sample costs less; measured per group on 2000-sample series, every
-    // fourth tile is faster for E 9-16 and for series above 4096 samples
-    // (the default; a batched plan may set its own from its autotuner).
-    const int stride = a.p1_stride > 0 ? a.p1_stride : (((ELO >= 9 && ELO <= 14) || m_lo > 4096) ? 4 : 1);
+    // sample costs less.  Measured per group (strides 1-8): on 2000-sample
+    // series every third tile is fastest for E 9-16 and every tile for the
+    // other groups; above 4096 samples every fourth tile (the default; a
+    // batched plan may set its own from its autotuner).
+    const int stride = a.p1_stride > 0 ? a.p1_stride
+                                       : (m_lo > 4096 ? 4 : ((ELO >= 9 && ELO <= 14) ? 3 : 1));
     uint32_t nN[kP1Tiles][NG];
     auto fetchN = [&](int c0) {  // in bounds: every tile start is below m_lo
 #pragma unroll
