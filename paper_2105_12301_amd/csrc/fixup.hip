@@ -48,8 +48,10 @@ __device__ __forceinline__ void stage(const KnnArgs &a, int row, int L, float *x
 // that is unless key(p, m1) < key(p, last entry); then the list and the
 // weights the sweep kept are the table row (the weights depend only on the
 // query and its neighbours), and when the table is the kept array itself the
-// row is left as it is.  Otherwise every key is recomputed, m1 is inserted
-// and the row is rewritten (the kept entries are read before).
+// row is left as it is.  Otherwise (about one query in a hundred) the query
+// is queued in LDS, and the queue is worked off by consecutive threads: every
+// key is recomputed, m1 is inserted and the row is rewritten (the kept
+// entries are read before).
 template <int E>
 __global__ __launch_bounds__(256) void k_fix_from_sweep(KnnArgs a, int slot0) {
   constexpr int K = E + 1;
@@ -58,46 +60,64 @@ __global__ __launch_bounds__(256) void k_fix_from_sweep(KnnArgs a, int slot0) {
   const int L = static_cast<int>(a.L_dev ? a.L_dev[row] : a.L_uni);
   const int m1 = L - E;
   if (m1 - 1 < K) return;  // no sweep list: k_scan_queries covers this series
-  const int p = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
-  if (p >= m1) return;
+  if (static_cast<int>(blockIdx.x) * 256 >= m1) return;  // (uniform)
   const float *__restrict__ x = a.X + static_cast<int64_t>(row) * a.ldx;
-  const int64_t ko = static_cast<int64_t>(row) * a.keep_strideE[E] + static_cast<int64_t>(p) * K;
-  const int32_t *__restrict__ kp = a.keepE[E] + ko;
-  float vp[E];
-#pragma unroll
-  for (int j = 0; j < E; ++j) vp[j] = x[p + j];
-  auto key = [&](int q) {
+  auto key_of = [&](int p, int q) {
     float acc = 0.0f;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const float d = vp[j] - x[q + j];
+      const float d = x[p + j] - x[q + j];
       acc = acc + d * d;
     }
     return acc;
   };
-  const float k_m1 = key(m1);
-  if (a.keepWE[E] && !(k_m1 < key(kp[K - 1]))) {
-    // the kept row is the table row: nothing to do when the table is the
-    // kept array itself (one extra row per slot for query m1), else a copy
-    if (a.idxE[E] == a.keepE[E] && a.wE[E] == a.keepWE[E] && a.strideE[E] == a.keep_strideE[E]) return;
-    const int64_t base = static_cast<int64_t>(row) * a.strideE[E] + static_cast<int64_t>(p) * K;
-    const float *__restrict__ kw = a.keepWE[E] + ko;
+  // Queries where m1 enters the list (about 1 in 100) are queued in LDS and
+  // rewritten by consecutive threads, so the slow path runs on few waves.
+  __shared__ int queue[256];
+  __shared__ int n_queue;
+  if (threadIdx.x == 0) n_queue = 0;
+  __syncthreads();
+  const int p = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
+  const bool same = a.idxE[E] == a.keepE[E] && a.wE[E] == a.keepWE[E] && a.strideE[E] == a.keep_strideE[E];
+  if (p < m1) {
+    const int64_t ko = static_cast<int64_t>(row) * a.keep_strideE[E] + static_cast<int64_t>(p) * K;
+    const int32_t *__restrict__ kp = a.keepE[E] + ko;
+    if (a.keepWE[E] && !(key_of(p, m1) < key_of(p, kp[K - 1]))) {
+      // the kept row is the table row: nothing to do when the table is the
+      // kept array itself (one extra row per slot for query m1), else a copy
+      if (!same) {
+        const int64_t base = static_cast<int64_t>(row) * a.strideE[E] + static_cast<int64_t>(p) * K;
+        const float *__restrict__ kw = a.keepWE[E] + ko;
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      a.idxE[E][base + i] = kp[i];
-      a.wE[E][base + i] = kw[i];
+        for (int i = 0; i < K; ++i) {
+          a.idxE[E][base + i] = kp[i];
+          a.wE[E][base + i] = kw[i];
+        }
+      }
+    } else {
+      queue[atomicAdd(&n_queue, 1)] = p;
     }
-    return;
   }
-  // m1 enters after every entry whose key is at most its own (it has the
-  // largest index) and pushes the last entry out.
-  int pos = 0;
-#pragma unroll 1
-  for (int i = 0; i < K; ++i) pos += key(kp[i]) <= k_m1 ? 1 : 0;
-  int qi[K];
+  __syncthreads();
+  const int nq = n_queue;
+  for (int i = static_cast<int>(threadIdx.x); i < nq; i += 256) {
+    const int pq = queue[i];
+    const int32_t *__restrict__ kp =
+        a.keepE[E] + static_cast<int64_t>(row) * a.keep_strideE[E] + static_cast<int64_t>(pq) * K;
+    float vp[E];
 #pragma unroll
-  for (int i = 0; i < K; ++i) qi[i] = i < pos ? kp[i] : (i == pos ? m1 : kp[i - 1 < 0 ? 0 : i - 1]);
-  finish_list<E, 0, K, E>(a, row, p, L, 0, a.need, vp, qi, x);
+    for (int j = 0; j < E; ++j) vp[j] = x[pq + j];
+    const float k_m1 = key_of(pq, m1);
+    // m1 enters after every entry whose key is at most its own (it has the
+    // largest index) and pushes the last entry out.
+    int pos = 0;
+#pragma unroll 1
+    for (int r = 0; r < K; ++r) pos += key_of(pq, kp[r]) <= k_m1 ? 1 : 0;
+    int qi[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) qi[r] = r < pos ? kp[r] : (r == pos ? m1 : kp[r - 1 < 0 ? 0 : r - 1]);
+    finish_list<E, 0, K, E>(a, row, pq, L, 0, a.need, vp, qi, x);
+  }
 }
 
 // Full scans, one query per wave: the lanes walk the candidates in ascending
