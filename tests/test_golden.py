@@ -1,0 +1,51 @@
+"""The oracle against the hand-worked examples of tests/golden/ (CPU).
+
+The fixtures were worked out by hand from Section 2.1 steps 1-4 and
+Algorithms 1-3 (exact integer neighbour tables and squared distances, closed-
+form weights), so they pin the oracle to something other than itself: a
+transposed embedding, a wrong horizon offset, a tie broken the other way, a
+dropped normalisation or a wrong Pearson term each changes a stored value.
+"""
+import numpy as np
+import pytest
+
+from golden_io import load
+from oracle import edm_oracle as O
+
+CASES = load()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_table_and_keys(name):
+    c = CASES[name]
+    x = c["x"].astype(np.float32)
+    idx, key = O.knn(x, c["E"], c["tau"], c["Tp"], c["k"])
+    assert np.array_equal(idx, c["idx"].astype(np.int32))
+    assert np.array_equal(key, c["key"].astype(np.float32))
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_weights_prediction_rho(name):
+    c = CASES[name]
+    x = c["x"].astype(np.float32)
+    idx = c["idx"].astype(np.int64)
+    D, w = O.weights(x, idx, c["E"], c["tau"])
+    assert np.allclose(D, np.sqrt(c["key"]), rtol=0, atol=1e-15)
+    assert np.allclose(w, c["w"], rtol=0, atol=1e-15)
+    pred, obs = O.lookup(idx, w, c["y"], c["E"], c["tau"], c["Tp"])
+    assert np.array_equal(obs, c["obs"])
+    assert np.allclose(pred, c["pred"], rtol=0, atol=1e-13)
+    assert abs(O.pearson(obs, pred) - c["rho"][0]) < 1e-13
+    assert abs(O.simplex_rho(x, c["y"], c["E"], c["tau"], c["Tp"], c["k"]) - c["rho"][0]) < 1e-13
+
+
+def test_ccm_pair():
+    # The cross map of Section 3.4 with the target's E equal to the case's E
+    # reaches the same pair: library A.x, target A.y (k = E + 1 in case A).
+    c = CASES["A"]
+    assert c["k"] == c["E"] + 1
+    X = c["x"][None, :].astype(np.float32)
+    Y = c["y"][None, :].astype(np.float32)
+    L = np.array([X.shape[1]])
+    rho = O.ccm(X, L, Y, L, np.array([c["E"]]), tau=c["tau"], Tp=c["Tp"])
+    assert abs(rho[0, 0] - c["rho"][0]) < 1e-13

@@ -1,0 +1,50 @@
+"""The HIP path (through the C ABI) against the hand-worked examples of
+tests/golden/: exact neighbour tables, distances and weights to float32
+rounding, predictions and rho within 1e-5, in every form."""
+import numpy as np
+import pytest
+
+from golden_io import load
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CASES = load()
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def edm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_12301_amd import edm as _edm
+
+    _edm.load_library()
+    return _edm
+
+
+def dev(a, dtype=np.float32):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+@pytest.mark.parametrize("form", [0, 1, 2, 3])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_worked_example(edm, name, form):
+    c = CASES[name]
+    ctx = edm.Context(device=0, form=form)
+    try:
+        x, y = dev(c["x"]), dev(c["y"])
+        idx, dist, w = edm.edm_knn(x, c["E"], c["tau"], c["Tp"], c["k"], ctx=ctx)
+        assert np.array_equal(idx.cpu().numpy(), c["idx"].astype(np.int32))
+        assert np.allclose(dist.cpu().numpy(), np.sqrt(c["key"]), rtol=1e-6, atol=0)
+        assert np.allclose(w.cpu().numpy(), c["w"], rtol=0, atol=1e-6)
+        pred, rho = edm.edm_lookup(idx, w, y, c["E"], c["tau"], c["Tp"], want_pred=True,
+                                   ctx=ctx)
+        assert np.allclose(pred.cpu().numpy()[0], c["pred"], rtol=0, atol=TOL)
+        assert abs(float(rho.cpu()[0]) - c["rho"][0]) < TOL
+        if c["k"] == c["E"] + 1:
+            r = edm.edm_ccm(x[None, :], dev([c["E"]], np.int32), Y=y[None, :],
+                            tau=c["tau"], Tp=c["Tp"], ctx=ctx)
+            assert abs(float(r.cpu()[0, 0]) - c["rho"][0]) < TOL
+    finally:
+        ctx.close()
