@@ -19,7 +19,7 @@ CASES = load()
 def test_table_and_keys(name):
     c = CASES[name]
     x = c["x"].astype(np.float32)
-    idx, key = O.knn(x, c["E"], c["tau"], c["Tp"], c["k"])
+    idx, key = O.knn(x, c["E"], c["tau"], c["Tp"], c["k"], excl=c.get("excl", 0))
     assert np.array_equal(idx, c["idx"].astype(np.int32))
     assert np.array_equal(key, c["key"].astype(np.float32))
 
@@ -36,16 +36,18 @@ def test_weights_prediction_rho(name):
     assert np.array_equal(obs, c["obs"])
     assert np.allclose(pred, c["pred"], rtol=0, atol=1e-13)
     assert abs(O.pearson(obs, pred) - c["rho"][0]) < 1e-13
-    assert abs(O.simplex_rho(x, c["y"], c["E"], c["tau"], c["Tp"], c["k"]) - c["rho"][0]) < 1e-13
+    r = O.simplex_rho(x, c["y"], c["E"], c["tau"], c["Tp"], c["k"], excl=c.get("excl", 0))
+    assert abs(r - c["rho"][0]) < 1e-13
 
 
-def test_ccm_pair():
+@pytest.mark.parametrize("name", ["A", "A_excl1"])
+def test_ccm_pair(name):
     # The cross map of Section 3.4 with the target's E equal to the case's E
-    # reaches the same pair: library A.x, target A.y (k = E + 1 in case A).
-    c = CASES["A"]
+    # reaches the same pair: library x, target y (k = E + 1 in these cases).
+    c = CASES[name]
     assert c["k"] == c["E"] + 1
     X = c["x"][None, :].astype(np.float32)
     Y = c["y"][None, :].astype(np.float32)
     L = np.array([X.shape[1]])
-    rho = O.ccm(X, L, Y, L, np.array([c["E"]]), tau=c["tau"], Tp=c["Tp"])
+    rho = O.ccm(X, L, Y, L, np.array([c["E"]]), tau=c["tau"], Tp=c["Tp"], excl=c.get("excl", 0))
     assert abs(rho[0, 0] - c["rho"][0]) < 1e-13
