@@ -4,7 +4,8 @@ The fixtures were worked out by hand from Section 2.1 steps 1-4 and
 Algorithms 1-3 (exact integer neighbour tables and squared distances, closed-
 form weights), so they pin the oracle to something other than itself: a
 transposed embedding, a wrong horizon offset, a tie broken the other way, a
-dropped normalisation or a wrong Pearson term each changes a stored value.
+dropped normalisation, a wrong Pearson term, an exclusion window off by one or
+a subsample that leaks other candidates each changes a stored value.
 """
 import numpy as np
 import pytest
@@ -15,11 +16,18 @@ from oracle import edm_oracle as O
 CASES = load()
 
 
+def table(c):
+    x = c["x"].astype(np.float32)
+    if "subset" in c:
+        return O.knn_subset(x, c["E"], c["tau"], c["Tp"], c["subset"].astype(np.int64), c["k"],
+                            excl=c.get("excl", 0))
+    return O.knn(x, c["E"], c["tau"], c["Tp"], c["k"], excl=c.get("excl", 0))
+
+
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_table_and_keys(name):
     c = CASES[name]
-    x = c["x"].astype(np.float32)
-    idx, key = O.knn(x, c["E"], c["tau"], c["Tp"], c["k"], excl=c.get("excl", 0))
+    idx, key = table(c)
     assert np.array_equal(idx, c["idx"].astype(np.int32))
     assert np.array_equal(key, c["key"].astype(np.float32))
 
@@ -36,7 +44,11 @@ def test_weights_prediction_rho(name):
     assert np.array_equal(obs, c["obs"])
     assert np.allclose(pred, c["pred"], rtol=0, atol=1e-13)
     assert abs(O.pearson(obs, pred) - c["rho"][0]) < 1e-13
-    r = O.simplex_rho(x, c["y"], c["E"], c["tau"], c["Tp"], c["k"], excl=c.get("excl", 0))
+    if "subset" in c:
+        r = O.ccm_subsample(x, c["y"], c["E"], c["tau"], c["Tp"], [c["subset"].astype(np.int64)],
+                            c["k"], excl=c.get("excl", 0))[0]
+    else:
+        r = O.simplex_rho(x, c["y"], c["E"], c["tau"], c["Tp"], c["k"], excl=c.get("excl", 0))
     assert abs(r - c["rho"][0]) < 1e-13
 
 
@@ -51,3 +63,11 @@ def test_ccm_pair(name):
     L = np.array([X.shape[1]])
     rho = O.ccm(X, L, Y, L, np.array([c["E"]]), tau=c["tau"], Tp=c["Tp"], excl=c.get("excl", 0))
     assert abs(rho[0, 0] - c["rho"][0]) < 1e-13
+
+
+def test_full_subset_is_case_A():
+    # The subsample of every candidate is the plain table (case A).
+    c = CASES["A"]
+    x = c["x"].astype(np.float32)
+    idx, _ = O.knn_subset(x, c["E"], c["tau"], c["Tp"], np.arange(6), c["k"])
+    assert np.array_equal(idx, c["idx"].astype(np.int32))

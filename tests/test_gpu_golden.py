@@ -29,7 +29,7 @@ def dev(a, dtype=np.float32):
 
 
 @pytest.mark.parametrize("form", [0, 1, 2, 3])
-@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("name", sorted(n for n in CASES if "subset" not in CASES[n]))
 def test_worked_example(edm, name, form):
     c = CASES[name]
     ctx = edm.Context(device=0, form=form)
@@ -48,5 +48,20 @@ def test_worked_example(edm, name, form):
             r = edm.edm_ccm(x[None, :], dev([c["E"]], np.int32), Y=y[None, :],
                             tau=c["tau"], Tp=c["Tp"], ctx=ctx)
             assert abs(float(r.cpu()[0, 0]) - c["rho"][0]) < TOL
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("name", sorted(n for n in CASES if "subset" in CASES[n]))
+def test_worked_subsample(edm, name):
+    c = CASES[name]
+    ctx = edm.Context(device=0)
+    ctx.set_exclusion_radius(c.get("excl", 0))
+    try:
+        rho, idx = edm.edm_ccm_subsample(dev(c["x"]), dev(c["y"]), c["E"],
+                                         [c["subset"].astype(np.int32)], tau=c["tau"],
+                                         Tp=c["Tp"], want_idx=True, ctx=ctx)
+        assert np.array_equal(idx.cpu().numpy()[0], c["idx"].astype(np.int32))
+        assert abs(float(rho.cpu()[0, 0]) - c["rho"][0]) < TOL
     finally:
         ctx.close()
