@@ -6,7 +6,7 @@ import os
 import numpy as np
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-INTS = ("E", "tau", "Tp", "k", "excl")
+INTS = ("E", "tau", "Tp", "k", "excl", "E_max", "E_opt")
 
 
 def load(name="worked_examples.txt"):

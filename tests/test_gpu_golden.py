@@ -29,7 +29,8 @@ def dev(a, dtype=np.float32):
 
 
 @pytest.mark.parametrize("form", [0, 1, 2, 3])
-@pytest.mark.parametrize("name", sorted(n for n in CASES if "subset" not in CASES[n]))
+@pytest.mark.parametrize("name", sorted(n for n in CASES
+                                         if "idx" in CASES[n] and "subset" not in CASES[n]))
 def test_worked_example(edm, name, form):
     c = CASES[name]
     ctx = edm.Context(device=0, form=form)
@@ -63,5 +64,25 @@ def test_worked_subsample(edm, name):
                                          Tp=c["Tp"], want_idx=True, ctx=ctx)
         assert np.array_equal(idx.cpu().numpy()[0], c["idx"].astype(np.int32))
         assert abs(float(rho.cpu()[0, 0]) - c["rho"][0]) < TOL
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("form", [0, 1, 2, 3])
+def test_worked_sweep(edm, form):
+    c = CASES["S"]
+    ctx = edm.Context(device=0, form=form)
+    try:
+        x = dev(c["x"])
+        for E in (1, 3):
+            idx, _, _ = edm.edm_knn(x, E, c["tau"], c["Tp"], ctx=ctx)
+            assert np.array_equal(idx.cpu().numpy(), c[f"idx_E{E}"].astype(np.int32)), E
+        rho, E_opt = edm.edm_simplex_sweep(x[None, :], E_max=c["E_max"], tau=c["tau"],
+                                           Tp=c["Tp"], ctx=ctx)
+        got, want = rho.cpu().numpy()[0].astype(np.float64), c["rho_sweep"]
+        assert np.array_equal(np.isnan(got), np.isnan(want))
+        ok = ~np.isnan(want)
+        assert np.allclose(got[ok], want[ok], rtol=0, atol=TOL)
+        assert int(E_opt.cpu()[0]) == c["E_opt"]
     finally:
         ctx.close()
