@@ -838,6 +838,11 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     // The next tile's products are issued before this tile's survivors are
     // queued, so the two overlap.  Products issued before a re-rank use the
     // older (larger) thresholds: more survivors, never fewer.
+    // The tile step (loads, products, queueing) runs at a raised wave
+    // priority and the re-rank at the normal one: of the two waves a SIMD
+    // holds, the one with products to issue goes first, and the other's
+    // re-rank fills the matrix core's latency (2.5 % off the filter on the
+    // 10000 x 2000 step; results unchanged).
     uint32_t e[16];
     load_tile(0, 32);
     estimates(e);
@@ -845,6 +850,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
     for (int c0 = 0; c0 < m_lo; c0 += 32) {
       const int cn = c0 + 32 < m_lo ? c0 + 32 : c0;  // the last step repeats a tile, unused
       uint32_t e_next[16];
+      __builtin_amdgcn_s_setprio(1);
       load_tile(cn, cn + 32);
       estimates(e_next);
       uint32_t bits = sign_mask(e);
@@ -852,6 +858,7 @@ __device__ __forceinline__ void gram_scan(const KnnArgs &a, const int row, const
       qbuf[cnt * kWave] = bits | tile_code(static_cast<uint32_t>(c0) >> 5);
       cnt += bits != 0u;
       nsv += __builtin_popcount(bits);
+      __builtin_amdgcn_s_setprio(0);
       if (__builtin_amdgcn_ballot_w64(cnt == kQueueCap)) flush();
 #pragma unroll
       for (int v = 0; v < 16; ++v) e[v] = e_next[v];
